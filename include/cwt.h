@@ -1,0 +1,175 @@
+/*
+ * cwt.h -- C ABI of libcwth, a hop-strided continuous wavelet transform
+ * (CWTH) for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper: Sec. II-A, Eq. (1) and its discrete form; Sec. II-B
+ * for the hop size H):
+ *
+ *     W[i][k] = sum_{m=-M_i}^{M_i} t_i[m] * x~[k*hop + m],
+ *     t_i[m]  = psi(m / s_i) / sqrt(s_i),   psi(u) = exp(-u^2/2) * cos(5u),
+ *     M_i     = floor(8 * s_i),  x~[j] = x[j] for 0 <= j < len, else 0,
+ *     k       = 0 .. K-1,  K = ceil(len / hop).
+ *
+ * hop = 1 is the full CWT; any hop gives exactly every hop-th column of it.
+ * The scalogram is S = |W| (the default output), stored row-major
+ * [n_scales][K] in the caller's scale order.  Scales are in samples; fs only
+ * maps scale to frequency, f_i = (5 / (2*pi)) * fs / s_i.
+ *
+ * Conventions for every function below:
+ *   - Every call returns a cwt_status; nothing aborts or throws across the ABI.
+ *     cwt_last_error() returns a thread-local message for the last failure.
+ *   - Pointers named x, out, xs[], outs[] are DEVICE pointers owned by the
+ *     caller; they must stay valid until the work queued on `stream`
+ *     completes.  All other pointers are HOST pointers; their contents are
+ *     copied before the call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   - Arguments are validated before anything is launched.
+ */
+#ifndef CWT_H
+#define CWT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cwt_plan_s* cwt_plan_t;   /* opaque, owned by the library */
+typedef struct cwt_batch_s* cwt_batch_t; /* opaque, owned by the library */
+
+typedef enum {
+    CWT_OK = 0,
+    CWT_ERR_INVALID_ARG = 1,   /* a bad argument; nothing was launched          */
+    CWT_ERR_UNSUPPORTED = 2,   /* unknown wavelet/dtype, or a batch mixing plans */
+    CWT_ERR_OUT_OF_MEMORY = 3, /* a device or pinned allocation failed           */
+    CWT_ERR_DEVICE = 4,        /* no usable gfx950 device, or a launch failed    */
+    CWT_ERR_INTERNAL = 5
+} cwt_status;
+
+typedef enum { CWT_WAVELET_MORLET = 0 } cwt_wavelet; /* psi(t)=exp(-t^2/2)cos(5t), |t|<=8 */
+
+typedef enum {
+    CWT_DTYPE_FP32 = 0,    /* plain FP32 direct sum on the vector ALUs                */
+    CWT_DTYPE_BF16 = 1,    /* BF16 operands on MFMA, FP32 accumulation                */
+    CWT_DTYPE_FP16 = 2,    /* FP16 operands on MFMA, FP32 accumulation                */
+    CWT_DTYPE_BF16X3 = 3,  /* hi+lo BF16 split, three MFMA products, FP32 accumulation */
+    CWT_DTYPE_FP8_E4M3 = 4 /* OCP e4m3 operands on MFMA; power-of-two scale per scale
+                              (taps) and per tile (signal), removed in the epilogue    */
+} cwt_dtype;
+
+typedef enum { CWT_OUT_MAGNITUDE = 0, CWT_OUT_SIGNED = 1 } cwt_output;
+
+/*
+ * Create a plan: validates the scales, builds the device-resident wavelet bank
+ * (taps evaluated in FP64 on the device, Eq. (1), then rounded once to the
+ * operand type) and picks a kernel configuration.  Banks are shared between
+ * plans with the same (fs, wavelet, scales, dtype) and reference counted.
+ *   fs        sampling rate in Hz, > 0 and finite (used only for frequencies)
+ *   scales    n_scales host doubles, each finite and > 0, at most 2^20 / 8
+ *             (M_i = floor(8 s_i) <= 131072); duplicates allowed
+ *   hop       translation stride H >= 1 (Sec. II-B)
+ *   plan_out  receives the plan on CWT_OK; untouched otherwise
+ * Errors: CWT_ERR_INVALID_ARG (fs, scales, n_scales < 1 or > 4096, hop < 1,
+ * NULL pointers), CWT_ERR_UNSUPPORTED (wavelet, dtype), CWT_ERR_DEVICE (no
+ * gfx950 device), CWT_ERR_OUT_OF_MEMORY.
+ */
+cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
+                           int32_t n_scales, int32_t hop, cwt_dtype dtype,
+                           cwt_plan_t* plan_out);
+
+/* Output mode: magnitude |W| (default) or signed W.  Plans are otherwise
+ * immutable; change the mode only while no work using the plan is queued. */
+cwt_status cwt_plan_set_output(cwt_plan_t plan, cwt_output mode);
+
+/* Release a plan.  Synchronises the device first, so queued work that uses
+ * the plan's bank completes before the bank can be freed. NULL is a no-op. */
+cwt_status cwt_plan_destroy(cwt_plan_t plan);
+
+/* K = ceil(len / hop) for this plan; -1 on a NULL plan or len < 0. */
+int64_t cwt_num_frames(cwt_plan_t plan, int64_t len);
+
+/* Plan properties (host scalars). */
+int32_t cwt_plan_num_scales(cwt_plan_t plan); /* -1 on NULL */
+int32_t cwt_plan_hop(cwt_plan_t plan);        /* -1 on NULL */
+
+/* hz_out[i] = (5 / (2*pi)) * fs / s_i, i in caller order (host array). */
+cwt_status cwt_scale_frequencies(cwt_plan_t plan, double* hz_out);
+
+/*
+ * Queue the transform of one clip on `stream` (asynchronous, no allocation, no
+ * host synchronisation).
+ *   x    device float32[len]
+ *   out  device float32[n_scales * cwt_num_frames(plan, len)], written fully
+ * len == 0 is a no-op returning CWT_OK.  Errors: CWT_ERR_INVALID_ARG (NULL
+ * plan, len < 0, NULL x/out when len > 0, S*K overflowing int64),
+ * CWT_ERR_DEVICE (launch failure; asynchronous faults surface at the caller's
+ * next synchronisation).
+ */
+cwt_status cwt_execute(cwt_plan_t plan, const float* x, int64_t len, float* out,
+                       void* stream);
+
+/*
+ * Queue n clips as ONE persistent launch: clip c is transformed with plans[c]
+ * (its own hop) from xs[c] (device float32[lens[c]]) into outs[c] (device
+ * float32[n_scales * cwt_num_frames(plans[c], lens[c])]).  All plans must share
+ * dtype, output mode and scale set (CWT_ERR_UNSUPPORTED otherwise); hops may
+ * differ.  Each clip's result is bit-identical to cwt_execute of that clip.
+ * Uses a library-owned batch context for the calling thread and device; see
+ * cwt_batch_create for the explicit form.
+ */
+cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs,
+                             const int64_t* lens, float* const* outs, int32_t n,
+                             void* stream);
+
+/*
+ * Explicit batch context: owns pinned and device descriptor buffers sized for
+ * up to max_clips clips and a captured HIP graph (descriptor upload + the
+ * persistent launch) that cwt_batch_execute replays with new descriptor
+ * contents.  One context serves one stream at a time; calls on it are
+ * serialised by the host (a call waits until the previous replay has consumed
+ * its descriptors).
+ */
+cwt_status cwt_batch_create(int32_t max_clips, cwt_batch_t* batch_out);
+cwt_status cwt_batch_destroy(cwt_batch_t batch);
+/* Same contract as cwt_execute_batch; use_graph = 0 launches without a graph. */
+cwt_status cwt_batch_execute(cwt_batch_t batch, const cwt_plan_t* plans,
+                             const float* const* xs, const int64_t* lens,
+                             float* const* outs, int32_t n, int32_t use_graph,
+                             void* stream);
+
+/*
+ * Time the candidate kernel configurations for this plan at signal length len
+ * (synchronous; allocates scratch buffers of its own) and keep the fastest for
+ * the plan's (dtype, hop, scale-set) class.  Results are written to the JSON
+ * cache named by $CWTH_AUTOTUNE_CACHE (if set) keyed by device arch and CU
+ * count, and read back by later plan creations.  chosen_out (host, may be NULL)
+ * receives the index of the chosen configuration.
+ */
+cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out);
+
+/* Kernel configuration in use (index into the plan's candidate list) and the
+ * number of candidates; a forced choice (for tests) via cwt_plan_set_config. */
+int32_t cwt_plan_config(cwt_plan_t plan);
+int32_t cwt_plan_num_configs(cwt_plan_t plan);
+cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
+
+/*
+ * Read back the operand values the bank holds for caller scale `scale_index`,
+ * decoded to double: taps_out[m + M] for m = -M .. M (host array of 2M+1).
+ * For CWT_DTYPE_BF16X3 the value is hi + lo; for FP8 it is the stored code
+ * times 1/alpha.  For checking the bank against the FP64 definition.
+ */
+cwt_status cwt_plan_bank_taps(cwt_plan_t plan, int32_t scale_index, double* taps_out,
+                              int64_t cap);
+
+const char* cwt_status_string(cwt_status s);
+const char* cwt_last_error(void);
+
+/* Library version string, e.g. "1.0.0 gfx950". */
+const char* cwt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CWT_H */

@@ -1,0 +1,135 @@
+// Internal declarations shared by the host side of libcwth and its kernels.
+// Nothing here is part of the public ABI (include/cwt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cwth {
+
+// ---------------------------------------------------------------------------
+// Operand types of the contraction.  Values match cwt_dtype.
+enum Dtype : int { DT_FP32 = 0, DT_BF16 = 1, DT_FP16 = 2, DT_BF16X3 = 3, DT_FP8 = 4 };
+
+// Rows of a 32-scale MFMA block, and the tile geometry of the direct kernel.
+constexpr int kBlockRows = 32;     // scales per MFMA block (the M side of 32x32xK)
+constexpr int kWaveSize = 64;
+constexpr int kMfmaWaves = 4;      // waves per MFMA work-group (split along frames)
+constexpr int kMaxGroupBlocks = 4; // blocks one MFMA work-group contracts at once
+constexpr int kDirectFrames = 64;  // frames per direct-sum work-group (one per lane)
+constexpr int kDirectRows = 4;     // scales per direct-sum wave
+constexpr int kDirectWaves = 4;    // waves per direct-sum work-group
+constexpr int kDirectChunk = 128;  // taps staged per LDS chunk in the direct kernel
+
+// K (taps) consumed by one MFMA for the operand type.
+__host__ __device__ constexpr int kstep_of(int dt) { return dt == DT_FP8 ? 64 : 16; }
+
+// ---------------------------------------------------------------------------
+// Wavelet bank layouts (built on the device by bank.hip, read by the kernels).
+//
+// Scales are sorted by half-width M (ascending); `rows` map sorted positions
+// back to the caller's row index (-1 for padding rows).
+//
+// Direct (FP32) bank: groups of kDirectRows consecutive sorted scales.  Group
+// g stores taps for m = -P_g .. P_g (P_g = max M in the group) as
+// taps[off_g + (m + P_g) * kDirectRows + r], zero outside each scale's own
+// support.
+struct DirectGroup {
+    int32_t P;         // padded half-width of the group
+    int32_t rows[kDirectRows];
+    int64_t off;       // float offset into the bank
+};
+
+// MFMA bank: blocks of kBlockRows sorted scales.  Block b covers K-steps
+// ks = lo .. hi (taps m in [kstep*ks, kstep*(ks+1)) ); for every step it stores
+// one A-operand fragment in exact lane order (64 lanes x fragment bytes), so a
+// wave loads it with one coalesced access per lane.  BF16X3 stores the hi
+// fragment followed by the lo fragment.
+struct MfmaBlock {
+    int32_t lo, hi;        // K-step range (nested: all ranges are symmetric about 0)
+    int64_t frag_off;      // byte offset of step `lo` in the fragment buffer
+    int32_t rows[kBlockRows];
+    float inv_alpha[kBlockRows]; // FP8 only: 1/alpha_r; 1 otherwise
+};
+
+// A group is what one work-group contracts: up to kMaxGroupBlocks blocks with
+// nested K ranges, listed by ascending range (so the blocks active at step ks
+// are a suffix of the list).
+struct MfmaGroup {
+    int32_t nblk;
+    int32_t blk[kMaxGroupBlocks]; // indices into the block table
+    int32_t lo, hi;               // union of the member ranges (= widest block)
+};
+
+// ---------------------------------------------------------------------------
+// Per-launch arguments.
+
+// One clip as seen by a kernel.
+struct ClipArg {
+    const float* x;
+    float* out;
+    int64_t len;     // samples
+    int64_t K;       // frames = ceil(len / hop)
+    int32_t hop;
+    int32_t ntile;   // frame tiles of this clip
+    int32_t mode;    // staging mode for the MFMA kernel (see StageMode)
+    int32_t copies;  // shifted copies (linear mode)
+    int32_t swz;     // XOR-swizzle shift (linear mode), -1 for none
+    int32_t pad;
+};
+
+enum StageMode : int { STAGE_LINEAR = 0, STAGE_ROWS = 1 };
+
+struct MfmaArgs {
+    const uint8_t* frags;
+    const MfmaBlock* blocks;
+    const MfmaGroup* groups;
+    int32_t ngroups;
+    int32_t signed_out;
+    int32_t chunk_steps;   // K-steps staged per LDS chunk
+    int32_t frames;        // frames per tile (= 32 * A * kMfmaWaves)
+    int32_t buf_bytes;     // bytes of one LDS staging buffer
+    int32_t xcd_remap;     // 1: map consecutive tiles to the same XCD
+    // single clip (grid launch)
+    ClipArg clip;
+    // batch (persistent launch)
+    const ClipArg* clips;  // device array, longest-first order
+    const int32_t* tile_prefix; // device: tile_prefix[c] = first tile of clip c (n+1 entries)
+    int32_t nclips;
+    int32_t total_tiles;   // tiles over all clips and groups
+    int32_t* counter;      // device work counter pair {next, done}
+};
+
+struct DirectArgs {
+    const float* taps;
+    const DirectGroup* groups;
+    int32_t ngroups;
+    int32_t signed_out;
+    ClipArg clip;
+    int32_t xcd_remap;
+};
+
+// Host-side launchers (defined in the .hip files).
+hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
+// cfgA = frame blocks per wave (1, 2, 4); nb = blocks per group bound (1, 2, 4).
+hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,
+                       int grid, hipStream_t s);
+int mfma_max_lds_bytes();
+// Resident work-groups per CU for a kernel instance with `shm` bytes of dynamic LDS.
+int mfma_occupancy(int dt, int A, int nb, int persistent, size_t shm);
+
+// Bank generation (bank.hip).
+struct BankScale {      // one sorted scale as the generator sees it
+    double s;
+    int32_t M;
+};
+hipError_t gen_direct_bank(const double* d_scales_sorted, int nscales, const DirectGroup* d_groups,
+                           int ngroups, float* d_taps, int64_t total_floats, hipStream_t st);
+hipError_t gen_mfma_bank(int dt, const double* d_scales_sorted, int nscales,
+                         const MfmaBlock* d_blocks, int nblocks, uint8_t* d_frags,
+                         int64_t total_bytes, const double* d_alpha, hipStream_t st);
+hipError_t decode_bank_taps(int dt, const uint8_t* d_frags, const MfmaBlock* d_blocks,
+                            const float* d_direct, const DirectGroup* d_dgroups,
+                            int sorted_pos, int M, double* d_out, hipStream_t st);
+
+}  // namespace cwth

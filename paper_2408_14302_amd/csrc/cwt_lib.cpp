@@ -1,0 +1,946 @@
+// Host side of libcwth: argument checks, plans, the shared wavelet-bank cache,
+// launch geometry, batch contexts (descriptor upload + persistent launch,
+// optionally replayed from a captured HIP graph), the autotuner and the
+// exported C ABI declared in include/cwt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cwt.h"
+#include "cwt_internal.h"
+
+using namespace cwth;
+
+// ---------------------------------------------------------------------------
+// Status and thread-local error text.
+static thread_local std::string g_last_error;
+
+static cwt_status fail(cwt_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr, what)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            cwt_status st_ = (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation) \
+                                 ? CWT_ERR_OUT_OF_MEMORY                                 \
+                                 : CWT_ERR_DEVICE;                                       \
+            return fail(st_, std::string(what) + ": " + hipGetErrorString(e_));          \
+        }                                                                                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device facts, looked up once per device.
+struct DeviceInfo {
+    bool ok = false;
+    int cus = 0;
+    std::string arch;
+    std::string why;
+};
+
+static std::mutex g_dev_mu;
+static std::map<int, DeviceInfo> g_dev;
+
+static cwt_status current_device(int* dev, DeviceInfo* info) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1)
+        return fail(CWT_ERR_DEVICE, "no HIP device available");
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return fail(CWT_ERR_DEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(d);
+    if (it == g_dev.end()) {
+        DeviceInfo di;
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, d) != hipSuccess) {
+            di.why = "hipGetDeviceProperties failed";
+        } else {
+            di.arch = p.gcnArchName;
+            di.cus = p.multiProcessorCount;
+            di.ok = di.arch.rfind("gfx950", 0) == 0;
+            if (!di.ok) di.why = "device " + std::to_string(d) + " is " + di.arch + ", library is built for gfx950";
+        }
+        it = g_dev.emplace(d, di).first;
+    }
+    if (!it->second.ok) return fail(CWT_ERR_DEVICE, it->second.why);
+    *dev = d;
+    if (info) *info = it->second;
+    return CWT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel configurations.  MFMA: A = 32-frame blocks per wave (tile = 128*A
+// frames), chunk = K-steps staged per LDS buffer.
+struct MfmaCfg {
+    int A;
+    int chunk;
+};
+static const MfmaCfg kMfmaCfgs[] = {{1, 8}, {2, 8}, {1, 16}, {2, 16}, {2, 4}, {4, 4}};
+static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
+
+static int elem_bytes(int dt) { return dt == DT_FP8 ? 1 : 2; }
+static int planes_of(int dt) { return dt == DT_BF16X3 ? 2 : 1; }
+
+static int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Staging geometry of one clip for the MFMA kernel; mirrors make_geo() in mfma.hip.
+struct Staging {
+    int mode, copies, swz;
+    int64_t bytes;  // one LDS buffer (all planes)
+};
+
+static Staging staging_for(int dt, int hop, int F, int chunk) {
+    const int U = 16 / elem_bytes(dt), KS = kstep_of(dt), P = planes_of(dt);
+    Staging s;
+    const int gh = (int)gcd64(hop, U);
+    s.copies = U / gh;
+    int64_t pmax = (int64_t)(F - 1) * hop + (int64_t)KS * chunk - 1;
+    int64_t len_u = ((pmax / U + 1) + 15) & ~int64_t(15);
+    int64_t cs = len_u + (s.copies > 1 ? 16 / s.copies : 0);
+    int64_t lin = (int64_t)s.copies * cs * 16 * P;
+    int64_t rows = (int64_t)F * (KS * chunk / U + 1) * 16 * P;
+    bool pow2 = (hop & (hop - 1)) == 0;
+    int q = hop / U;
+    s.swz = -1;
+    bool lin_conflicts = false;
+    if (s.copies == 1 && hop % U == 0 && q % 2 == 0) {
+        if (pow2) {
+            int sh = 0;
+            while ((1 << sh) < q) ++sh;
+            s.swz = sh;
+        } else {
+            lin_conflicts = true;
+        }
+    }
+    if (lin <= rows && !lin_conflicts) {
+        s.mode = STAGE_LINEAR;
+        s.bytes = lin;
+    } else {
+        s.mode = STAGE_ROWS;
+        s.bytes = rows;
+        s.swz = -1;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Wavelet bank: device-resident, shared by plans with the same key.
+struct Bank {
+    int dt = 0;
+    int device = 0;
+    std::vector<double> scales;        // caller order
+    std::vector<int> sorted_to_caller; // sorted position -> caller row
+    std::vector<int> caller_to_sorted;
+    std::vector<int> M_sorted;
+    // direct
+    std::vector<DirectGroup> dgroups;
+    float* d_dtaps = nullptr;
+    DirectGroup* d_dgroups = nullptr;
+    // mfma
+    std::vector<MfmaBlock> blocks;
+    std::vector<MfmaGroup> groups;
+    int nb_max = 1;
+    uint8_t* d_frags = nullptr;
+    MfmaBlock* d_blocks = nullptr;
+    MfmaGroup* d_groups = nullptr;
+    int64_t frag_bytes = 0;
+    int Mmax = 0;
+
+    ~Bank() {
+        if (d_dtaps) (void)hipFree(d_dtaps);
+        if (d_dgroups) (void)hipFree(d_dgroups);
+        if (d_frags) (void)hipFree(d_frags);
+        if (d_blocks) (void)hipFree(d_blocks);
+        if (d_groups) (void)hipFree(d_groups);
+    }
+};
+
+typedef std::tuple<int, int, std::vector<double>> BankKey;
+static std::mutex g_bank_mu;
+static std::map<BankKey, std::weak_ptr<Bank>> g_banks;
+
+static cwt_status build_bank(int dt, int device, const std::vector<double>& scales,
+                             std::shared_ptr<Bank>* out) {
+    auto bk = std::make_shared<Bank>();
+    bk->dt = dt;
+    bk->device = device;
+    bk->scales = scales;
+    const int S = (int)scales.size();
+    std::vector<int> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        int Ma = (int)std::floor(8.0 * scales[a]), Mb = (int)std::floor(8.0 * scales[b]);
+        if (Ma != Mb) return Ma < Mb;
+        return scales[a] < scales[b];
+    });
+    bk->sorted_to_caller = order;
+    bk->caller_to_sorted.assign(S, 0);
+    std::vector<double> sorted(S);
+    for (int p = 0; p < S; ++p) {
+        bk->caller_to_sorted[order[p]] = p;
+        sorted[p] = scales[order[p]];
+        bk->M_sorted.push_back((int)std::floor(8.0 * sorted[p]));
+    }
+    bk->Mmax = bk->M_sorted.back();
+
+    double* d_sorted = nullptr;
+    double* d_alpha = nullptr;
+    HIP_TRY(hipMalloc(&d_sorted, sizeof(double) * S), "bank scales");
+    std::unique_ptr<double, void (*)(double*)> g1(d_sorted, [](double* p) { (void)hipFree(p); });
+    HIP_TRY(hipMemcpy(d_sorted, sorted.data(), sizeof(double) * S, hipMemcpyHostToDevice), "bank scales copy");
+
+    if (dt == DT_FP32) {
+        const int ng = (S + kDirectRows - 1) / kDirectRows;
+        int64_t off = 0;
+        for (int g = 0; g < ng; ++g) {
+            DirectGroup G;
+            G.P = 0;
+            for (int r = 0; r < kDirectRows; ++r) {
+                int p = g * kDirectRows + r;
+                G.rows[r] = p < S ? order[p] : -1;
+                if (p < S) G.P = std::max(G.P, bk->M_sorted[p]);
+            }
+            G.off = off;
+            off += (int64_t)(2 * G.P + 1) * kDirectRows;
+            bk->dgroups.push_back(G);
+        }
+        HIP_TRY(hipMalloc(&bk->d_dtaps, sizeof(float) * off), "direct bank");
+        HIP_TRY(hipMalloc(&bk->d_dgroups, sizeof(DirectGroup) * ng), "direct groups");
+        HIP_TRY(hipMemcpy(bk->d_dgroups, bk->dgroups.data(), sizeof(DirectGroup) * ng, hipMemcpyHostToDevice), "direct groups copy");
+        HIP_TRY(gen_direct_bank(d_sorted, S, bk->d_dgroups, ng, bk->d_dtaps, off, 0), "direct bank generation");
+    } else {
+        const int KS = kstep_of(dt);
+        const int step_bytes = planes_of(dt) * 64 * (dt == DT_FP8 ? 32 : 16);
+        const int nbk = (S + kBlockRows - 1) / kBlockRows;
+        std::vector<double> alpha(S, 1.0);
+        if (dt == DT_FP8) {
+            // alpha = 2^floor(log2(448 / max|t|)); max|t| = psi(0)/sqrt(s) = 1/sqrt(s).
+            for (int p = 0; p < S; ++p) {
+                int e;
+                std::frexp(448.0 * std::sqrt(sorted[p]), &e);
+                alpha[p] = std::ldexp(1.0, e - 1);
+            }
+        }
+        int64_t off = 0;
+        for (int b = 0; b < nbk; ++b) {
+            MfmaBlock B;
+            int Mb = 0;
+            for (int r = 0; r < kBlockRows; ++r) {
+                int p = b * kBlockRows + r;
+                B.rows[r] = p < S ? order[p] : -1;
+                B.inv_alpha[r] = p < S ? (float)(1.0 / alpha[p]) : 1.0f;
+                if (p < S) Mb = std::max(Mb, bk->M_sorted[p]);
+            }
+            // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb]
+            B.lo = (int)std::floor(-(double)Mb / KS);
+            B.hi = Mb / KS;
+            B.frag_off = off;
+            off += (int64_t)(B.hi - B.lo + 1) * step_bytes;
+            bk->blocks.push_back(B);
+        }
+        bk->frag_bytes = off;
+        // Groups of at most four blocks.  More than four blocks: deal blocks
+        // (widest first) to groups in snake order to balance the K-steps.
+        const int ngr = (nbk + kMaxGroupBlocks - 1) / kMaxGroupBlocks;
+        std::vector<std::vector<int>> members(ngr);
+        std::vector<int> byw(nbk);
+        std::iota(byw.begin(), byw.end(), 0);
+        std::sort(byw.begin(), byw.end(), [&](int a, int b) {
+            return bk->blocks[a].hi - bk->blocks[a].lo > bk->blocks[b].hi - bk->blocks[b].lo;
+        });
+        for (int i = 0; i < nbk; ++i) {
+            int round = i / ngr, pos = i % ngr;
+            int g = (round % 2 == 0) ? pos : ngr - 1 - pos;
+            members[g].push_back(byw[i]);
+        }
+        bk->nb_max = 1;
+        for (int g = 0; g < ngr; ++g) {
+            auto& m = members[g];
+            std::sort(m.begin(), m.end(), [&](int a, int b) {
+                return bk->blocks[a].hi - bk->blocks[a].lo < bk->blocks[b].hi - bk->blocks[b].lo;
+            });
+            MfmaGroup G;
+            G.nblk = (int)m.size();
+            for (int i = 0; i < kMaxGroupBlocks; ++i) G.blk[i] = i < G.nblk ? m[i] : 0;
+            G.lo = bk->blocks[m.back()].lo;
+            G.hi = bk->blocks[m.back()].hi;
+            bk->groups.push_back(G);
+            bk->nb_max = std::max(bk->nb_max, G.nblk);
+        }
+        HIP_TRY(hipMalloc(&d_alpha, sizeof(double) * S), "alpha");
+        std::unique_ptr<double, void (*)(double*)> g2(d_alpha, [](double* p) { (void)hipFree(p); });
+        HIP_TRY(hipMemcpy(d_alpha, alpha.data(), sizeof(double) * S, hipMemcpyHostToDevice), "alpha copy");
+        HIP_TRY(hipMalloc(&bk->d_frags, off), "mfma bank");
+        HIP_TRY(hipMalloc(&bk->d_blocks, sizeof(MfmaBlock) * nbk), "mfma blocks");
+        HIP_TRY(hipMalloc(&bk->d_groups, sizeof(MfmaGroup) * ngr), "mfma groups");
+        HIP_TRY(hipMemcpy(bk->d_blocks, bk->blocks.data(), sizeof(MfmaBlock) * nbk, hipMemcpyHostToDevice), "blocks copy");
+        HIP_TRY(hipMemcpy(bk->d_groups, bk->groups.data(), sizeof(MfmaGroup) * ngr, hipMemcpyHostToDevice), "groups copy");
+        HIP_TRY(gen_mfma_bank(dt, d_sorted, S, bk->d_blocks, nbk, bk->d_frags, off, d_alpha, 0), "mfma bank generation");
+        HIP_TRY(hipDeviceSynchronize(), "bank generation");
+    }
+    HIP_TRY(hipDeviceSynchronize(), "bank generation");
+    *out = bk;
+    return CWT_OK;
+}
+
+static cwt_status acquire_bank(int dt, int device, const std::vector<double>& scales,
+                               std::shared_ptr<Bank>* out) {
+    std::lock_guard<std::mutex> lk(g_bank_mu);
+    BankKey key(dt, device, scales);
+    auto it = g_banks.find(key);
+    if (it != g_banks.end()) {
+        if (auto sp = it->second.lock()) {
+            *out = sp;
+            return CWT_OK;
+        }
+    }
+    std::shared_ptr<Bank> bk;
+    cwt_status st = build_bank(dt, device, scales, &bk);
+    if (st != CWT_OK) return st;
+    g_banks[key] = bk;
+    *out = bk;
+    return CWT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans.
+struct cwt_plan_s {
+    double fs;
+    int hop;
+    int dt;
+    int signed_out = 0;
+    int cfg = 0;
+    int device = 0;
+    int cus = 0;
+    std::string arch;
+    std::shared_ptr<Bank> bank;
+};
+
+static std::string tune_key(const cwt_plan_s* p, int64_t len) {
+    // (arch, CUs, dtype, hop bucket, scale count, widest half-width bucket, length bucket)
+    auto bucket = [](int64_t v) {
+        int b = 0;
+        while ((int64_t(1) << (b + 1)) <= v) ++b;
+        return b;
+    };
+    std::ostringstream o;
+    o << p->arch << "/" << p->cus << "/dt" << p->dt << "/h" << bucket(p->hop) << "/S"
+      << p->bank->scales.size() << "/M" << bucket(std::max(1, p->bank->Mmax)) << "/N" << bucket(std::max<int64_t>(1, len));
+    return o.str();
+}
+
+static std::mutex g_tune_mu;
+
+static std::map<std::string, int> read_tune_cache() {
+    std::map<std::string, int> m;
+    const char* path = std::getenv("CWTH_AUTOTUNE_CACHE");
+    if (!path) return m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::string line;
+    // Format: one "key": index pair per line inside a JSON object.
+    while (std::getline(f, line)) {
+        size_t a = line.find('"');
+        size_t b = line.find('"', a + 1);
+        size_t c = line.find(':', b + 1);
+        if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
+        m[line.substr(a + 1, b - a - 1)] = std::atoi(line.c_str() + c + 1);
+    }
+    return m;
+}
+
+static void write_tune_cache(const std::map<std::string, int>& m) {
+    const char* path = std::getenv("CWTH_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    std::rename(tmp.c_str(), path);
+}
+
+static int default_cfg(int dt, int hop) {
+    if (dt == DT_FP32) return 0;
+    return hop <= 64 ? 1 : 0;   // {2,8} for small hops, {1,8} otherwise
+}
+
+static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
+    if (p->dt == DT_FP32) return cfg == 0;
+    if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
+    const MfmaCfg& c = kMfmaCfgs[cfg];
+    if (c.A == 4 && p->bank->nb_max > 2) return false;   // register budget
+    Staging s = staging_for(p->dt, hop, 128 * c.A, c.chunk);
+    return 2 * s.bytes <= mfma_max_lds_bytes() - 2048;
+}
+
+// ---------------------------------------------------------------------------
+// Launch of one clip.
+static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int F,
+                         int chunk, int64_t* bytes_out) {
+    ClipArg c;
+    std::memset(&c, 0, sizeof(c));
+    c.x = x;
+    c.out = out;
+    c.len = len;
+    c.hop = p->hop;
+    c.K = (len + p->hop - 1) / p->hop;
+    c.ntile = (int32_t)((c.K + F - 1) / F);
+    if (p->dt != DT_FP32) {
+        Staging s = staging_for(p->dt, p->hop, F, chunk);
+        c.mode = s.mode;
+        c.copies = s.copies;
+        c.swz = s.swz;
+        if (bytes_out) *bytes_out = s.bytes;
+    }
+    return c;
+}
+
+static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64_t len, float* out,
+                             hipStream_t stream) {
+    const Bank& bk = *p->bank;
+    if (p->dt == DT_FP32) {
+        DirectArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.taps = bk.d_dtaps;
+        a.groups = bk.d_dgroups;
+        a.ngroups = (int)bk.dgroups.size();
+        a.signed_out = p->signed_out;
+        a.clip = make_clip(p, x, len, out, kDirectFrames, 1, nullptr);
+        a.xcd_remap = 1;
+        HIP_TRY(launch_direct(a, stream), "direct launch");
+        return CWT_OK;
+    }
+    const MfmaCfg& c = kMfmaCfgs[cfg];
+    const int F = 128 * c.A;
+    MfmaArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.frags = bk.d_frags;
+    a.blocks = bk.d_blocks;
+    a.groups = bk.d_groups;
+    a.ngroups = (int)bk.groups.size();
+    a.signed_out = p->signed_out;
+    a.chunk_steps = c.chunk;
+    a.frames = F;
+    int64_t bytes = 0;
+    a.clip = make_clip(p, x, len, out, F, c.chunk, &bytes);
+    a.buf_bytes = (int32_t)bytes;
+    a.xcd_remap = 1;
+    int64_t grid = (int64_t)a.clip.ntile * a.ngroups;
+    if (grid > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
+    HIP_TRY(launch_mfma(p->dt, c.A, bk.nb_max, a, 0, (int)grid, stream), "mfma launch");
+    return CWT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch contexts.
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr;
+    hipGraphNode_t kernel_node = nullptr;
+};
+
+struct cwt_batch_s {
+    int device = 0;
+    int max_clips = 0;
+    int cus = 0;
+    size_t desc_cap = 0;
+    uint8_t* pinned[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+    int flip = 0;
+    uint8_t* d_desc = nullptr;
+    int32_t* d_counter = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::tuple<int, int, int, int, int, int>, GraphEntry> graphs;
+    std::mutex mu;
+
+    ~cwt_batch_s() {
+        for (int i = 0; i < 2; ++i) {
+            if (done[i]) {
+                (void)hipEventSynchronize(done[i]);
+                (void)hipEventDestroy(done[i]);
+            }
+            if (pinned[i]) (void)hipHostFree(pinned[i]);
+        }
+        for (auto& kv : graphs) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+        }
+        if (d_desc) (void)hipFree(d_desc);
+        if (d_counter) (void)hipFree(d_counter);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+// Descriptor buffer: [int32 nclips, int32 total_tiles, pad to 16] [ClipArg x n] [int32 prefix x (n+1)]
+static size_t desc_bytes(int n) {
+    return 16 + sizeof(ClipArg) * (size_t)n + sizeof(int32_t) * (size_t)(n + 1) + 16;
+}
+
+static cwt_status batch_init(cwt_batch_s* b, int max_clips) {
+    DeviceInfo di;
+    cwt_status st = current_device(&b->device, &di);
+    if (st != CWT_OK) return st;
+    b->cus = di.cus;
+    b->max_clips = max_clips;
+    b->desc_cap = desc_bytes(max_clips);
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(hipHostMalloc((void**)&b->pinned[i], b->desc_cap, hipHostMallocDefault), "pinned descriptors");
+        HIP_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming), "batch event");
+    }
+    HIP_TRY(hipMalloc(&b->d_desc, b->desc_cap), "device descriptors");
+    HIP_TRY(hipMalloc(&b->d_counter, 2 * sizeof(int32_t)), "work counter");
+    HIP_TRY(hipMemset(b->d_counter, 0, 2 * sizeof(int32_t)), "work counter init");
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "capture stream");
+    HIP_TRY(hipDeviceSynchronize(), "batch init");
+    return CWT_OK;
+}
+
+// Persistent grid: enough work-groups to fill every CU at the kernel's occupancy.
+static int persistent_grid(int cus, int dt, int A, int nb, int64_t lds_bytes) {
+    int per_cu = mfma_occupancy(dt, A, nb, 1, (size_t)lds_bytes);
+    return cus * std::max(1, per_cu);
+}
+
+static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float* const* xs,
+                            const int64_t* lens, float* const* outs, int32_t n, int use_graph,
+                            hipStream_t stream) {
+    if (n < 0) return fail(CWT_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return CWT_OK;
+    if (!plans || !xs || !lens || !outs) return fail(CWT_ERR_INVALID_ARG, "NULL batch array");
+    if (n > b->max_clips) return fail(CWT_ERR_INVALID_ARG, "batch larger than the context's max_clips");
+    const cwt_plan_s* p0 = plans[0];
+    if (!p0) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+    for (int i = 0; i < n; ++i) {
+        const cwt_plan_s* p = plans[i];
+        if (!p) return fail(CWT_ERR_INVALID_ARG, "NULL plan in batch");
+        if (p->bank != p0->bank || p->signed_out != p0->signed_out)
+            return fail(CWT_ERR_UNSUPPORTED, "batch plans differ in dtype, scales or output mode");
+        if (lens[i] < 0) return fail(CWT_ERR_INVALID_ARG, "negative length in batch");
+        if (lens[i] > 0 && (!xs[i] || !outs[i])) return fail(CWT_ERR_INVALID_ARG, "NULL buffer in batch");
+        int64_t K = (lens[i] + p->hop - 1) / p->hop;
+        if (K > 0 && (int64_t)p->bank->scales.size() > INT64_MAX / K)
+            return fail(CWT_ERR_INVALID_ARG, "output size overflows int64");
+    }
+    if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
+    const Bank& bk = *p0->bank;
+
+    if (p0->dt == DT_FP32) {
+        // The plain path has no persistent kernel: one launch per clip.
+        for (int i = 0; i < n; ++i) {
+            if (lens[i] == 0) continue;
+            cwt_status st = launch_one(plans[i], 0, xs[i], lens[i], outs[i], stream);
+            if (st != CWT_OK) return st;
+        }
+        return CWT_OK;
+    }
+    // One configuration for the whole launch: the first plan's, shrunk until
+    // every clip's staging buffer fits.
+    int cfg = p0->cfg;
+    for (int tries = 0; tries < kNumMfmaCfgs; ++tries) {
+        bool ok = true;
+        for (int i = 0; i < n && ok; ++i) ok = cfg_fits(plans[i], cfg, plans[i]->hop);
+        if (ok) break;
+        cfg = (cfg + 1) % kNumMfmaCfgs;
+    }
+    const MfmaCfg& c = kMfmaCfgs[cfg];
+    const int F = 128 * c.A;
+
+    // Wait until the pinned buffer we are about to overwrite has been consumed.
+    const int slot = b->flip;
+    b->flip ^= 1;
+    if (b->used[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch reuse wait");
+    uint8_t* host = b->pinned[slot];
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i)
+        if (lens[i] > 0) order.push_back(i);
+    // Longest first (most tiles first) so the persistent grid drains evenly.
+    std::vector<ClipArg> clips(n);
+    int64_t maxbytes = 16;
+    for (int i : order) {
+        int64_t bytes = 0;
+        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], F, c.chunk, &bytes);
+        maxbytes = std::max(maxbytes, bytes);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return clips[a].ntile > clips[bq].ntile; });
+    const int nc = (int)order.size();
+    if (nc == 0) return CWT_OK;
+    ClipArg* hc = (ClipArg*)(host + 16);
+    int32_t* hp = (int32_t*)(host + 16 + sizeof(ClipArg) * nc);
+    int64_t total = 0;
+    for (int j = 0; j < nc; ++j) {
+        hc[j] = clips[order[j]];
+        hp[j] = (int32_t)total;
+        total += (int64_t)clips[order[j]].ntile * (int64_t)bk.groups.size();
+        if (total > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "batch has too many tiles");
+    }
+    hp[nc] = (int32_t)total;
+    ((int32_t*)host)[0] = nc;
+    ((int32_t*)host)[1] = (int32_t)total;
+    const size_t used_bytes = 16 + sizeof(ClipArg) * nc + sizeof(int32_t) * (nc + 1);
+
+    MfmaArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.frags = bk.d_frags;
+    a.blocks = bk.d_blocks;
+    a.groups = bk.d_groups;
+    a.ngroups = (int)bk.groups.size();
+    a.signed_out = p0->signed_out;
+    a.chunk_steps = c.chunk;
+    a.frames = F;
+    a.buf_bytes = (int32_t)maxbytes;
+    a.xcd_remap = 0;
+    // The descriptor pointers are fixed device addresses; counts live in the header.
+    a.clips = (const ClipArg*)(b->d_desc + 16);
+    a.tile_prefix = (const int32_t*)(b->d_desc + 16 + sizeof(ClipArg) * nc);
+    a.nclips = nc;
+    a.total_tiles = (int32_t)total;
+    a.counter = b->d_counter;
+    const int grid = persistent_grid(b->cus, p0->dt, c.A, bk.nb_max, 2 * maxbytes);
+
+    if (!use_graph) {
+        HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
+        HIP_TRY(launch_mfma(p0->dt, c.A, bk.nb_max, a, 1, grid, stream), "persistent launch");
+    } else {
+        // Kernel arguments that vary per batch (nclips, total tiles, prefix
+        // address) are part of the captured node, so graphs are cached per
+        // (shape) and their kernel node parameters refreshed before replay.
+        auto key = std::make_tuple(p0->dt, c.A, bk.nb_max, (int)maxbytes, grid, c.chunk);
+        GraphEntry& ge = b->graphs[key];
+        if (!ge.exec) {
+            HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+            hipError_t e1 = hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream);
+            hipError_t e2 = launch_mfma(p0->dt, c.A, bk.nb_max, a, 1, grid, b->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e3 = hipStreamEndCapture(b->cap_stream, &g);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                b->graphs.erase(key);
+                return fail(CWT_ERR_DEVICE, "graph capture failed");
+            }
+            ge.graph = g;
+            size_t nn = 0;
+            HIP_TRY(hipGraphGetNodes(g, nullptr, &nn), "graph nodes");
+            std::vector<hipGraphNode_t> nodes(nn);
+            HIP_TRY(hipGraphGetNodes(g, nodes.data(), &nn), "graph nodes");
+            for (auto nd : nodes) {
+                hipGraphNodeType t;
+                HIP_TRY(hipGraphNodeGetType(nd, &t), "graph node type");
+                if (t == hipGraphNodeTypeMemcpy) ge.copy_node = nd;
+                if (t == hipGraphNodeTypeKernel) ge.kernel_node = nd;
+            }
+            if (!ge.copy_node || !ge.kernel_node) return fail(CWT_ERR_INTERNAL, "unexpected graph shape");
+            HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0), "graph instantiate");
+        } else {
+            HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, b->d_desc, host, used_bytes,
+                                                      hipMemcpyHostToDevice), "graph copy update");
+            // Refresh the kernel node's argument block.
+            hipKernelNodeParams kp;
+            HIP_TRY(hipGraphKernelNodeGetParams(ge.kernel_node, &kp), "kernel node params");
+            void* args[1] = {&a};
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.kernel_node, &kp), "kernel node update");
+        }
+        HIP_TRY(hipGraphLaunch(ge.exec, stream), "graph launch");
+    }
+    HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
+    b->used[slot] = true;
+    return CWT_OK;
+}
+
+// Implicit batch contexts, one per (thread, device, stream).
+// They live until the process ends (never torn down after the HIP runtime).
+static thread_local std::map<std::pair<int, void*>, cwt_batch_s*> t_batches;
+
+// ---------------------------------------------------------------------------
+// Exported ABI.
+extern "C" {
+
+const char* cwt_status_string(cwt_status s) {
+    switch (s) {
+        case CWT_OK: return "CWT_OK";
+        case CWT_ERR_INVALID_ARG: return "CWT_ERR_INVALID_ARG";
+        case CWT_ERR_UNSUPPORTED: return "CWT_ERR_UNSUPPORTED";
+        case CWT_ERR_OUT_OF_MEMORY: return "CWT_ERR_OUT_OF_MEMORY";
+        case CWT_ERR_DEVICE: return "CWT_ERR_DEVICE";
+        case CWT_ERR_INTERNAL: return "CWT_ERR_INTERNAL";
+    }
+    return "CWT_ERR_UNKNOWN";
+}
+
+const char* cwt_last_error(void) { return g_last_error.c_str(); }
+
+const char* cwt_version(void) { return "1.0.0 gfx950"; }
+
+cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales, int32_t n_scales,
+                           int32_t hop, cwt_dtype dtype, cwt_plan_t* plan_out) {
+    try {
+        if (!plan_out) return fail(CWT_ERR_INVALID_ARG, "plan_out is NULL");
+        if (!(fs > 0.0) || !std::isfinite(fs)) return fail(CWT_ERR_INVALID_ARG, "fs must be finite and > 0");
+        if (n_scales < 1 || n_scales > 4096) return fail(CWT_ERR_INVALID_ARG, "n_scales must be in [1, 4096]");
+        if (!scales) return fail(CWT_ERR_INVALID_ARG, "scales is NULL");
+        if (hop < 1) return fail(CWT_ERR_INVALID_ARG, "hop must be >= 1");
+        for (int i = 0; i < n_scales; ++i) {
+            double s = scales[i];
+            if (!std::isfinite(s) || !(s > 0.0) || std::floor(8.0 * s) > 131072.0)
+                return fail(CWT_ERR_INVALID_ARG, "scale " + std::to_string(i) + " must be finite, > 0 and <= 16384");
+        }
+        if (wavelet != CWT_WAVELET_MORLET) return fail(CWT_ERR_UNSUPPORTED, "unknown wavelet");
+        if ((int)dtype < 0 || (int)dtype > 4) return fail(CWT_ERR_UNSUPPORTED, "unknown dtype");
+        DeviceInfo di;
+        int dev = 0;
+        cwt_status st = current_device(&dev, &di);
+        if (st != CWT_OK) return st;
+        std::vector<double> sc(scales, scales + n_scales);
+        auto p = std::make_unique<cwt_plan_s>();
+        p->fs = fs;
+        p->hop = hop;
+        p->dt = (int)dtype;
+        p->device = dev;
+        p->cus = di.cus;
+        p->arch = di.arch;
+        st = acquire_bank(p->dt, dev, sc, &p->bank);
+        if (st != CWT_OK) return st;
+        p->cfg = default_cfg(p->dt, hop);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto m = read_tune_cache();
+            // the length bucket of 10 s at 16 kHz is the default class
+            auto it = m.find(tune_key(p.get(), 160000));
+            if (it != m.end() && cfg_fits(p.get(), it->second, hop)) p->cfg = it->second;
+        }
+        if (!cfg_fits(p.get(), p->cfg, hop)) {
+            bool found = false;
+            for (int c = 0; c < (p->dt == DT_FP32 ? 1 : kNumMfmaCfgs); ++c)
+                if (cfg_fits(p.get(), c, hop)) {
+                    p->cfg = c;
+                    found = true;
+                    break;
+                }
+            if (!found) return fail(CWT_ERR_UNSUPPORTED, "no kernel configuration fits this hop");
+        }
+        *plan_out = p.release();
+        return CWT_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(CWT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+cwt_status cwt_plan_set_output(cwt_plan_t plan, cwt_output mode) {
+    if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+    if (mode != CWT_OUT_MAGNITUDE && mode != CWT_OUT_SIGNED) return fail(CWT_ERR_INVALID_ARG, "bad output mode");
+    plan->signed_out = mode == CWT_OUT_SIGNED;
+    return CWT_OK;
+}
+
+cwt_status cwt_plan_destroy(cwt_plan_t plan) {
+    if (!plan) return CWT_OK;
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return CWT_OK;
+}
+
+int64_t cwt_num_frames(cwt_plan_t plan, int64_t len) {
+    if (!plan || len < 0) return -1;
+    return (len + plan->hop - 1) / plan->hop;
+}
+
+int32_t cwt_plan_num_scales(cwt_plan_t plan) { return plan ? (int32_t)plan->bank->scales.size() : -1; }
+int32_t cwt_plan_hop(cwt_plan_t plan) { return plan ? plan->hop : -1; }
+
+cwt_status cwt_scale_frequencies(cwt_plan_t plan, double* hz_out) {
+    if (!plan || !hz_out) return fail(CWT_ERR_INVALID_ARG, "NULL argument");
+    const double fc = 5.0 / (2.0 * M_PI);
+    for (size_t i = 0; i < plan->bank->scales.size(); ++i) hz_out[i] = fc * plan->fs / plan->bank->scales[i];
+    return CWT_OK;
+}
+
+cwt_status cwt_execute(cwt_plan_t plan, const float* x, int64_t len, float* out, void* stream) {
+    try {
+        if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+        if (len < 0) return fail(CWT_ERR_INVALID_ARG, "len < 0");
+        if (len == 0) return CWT_OK;
+        if (!x || !out) return fail(CWT_ERR_INVALID_ARG, "NULL x or out");
+        int64_t K = (len + plan->hop - 1) / plan->hop;
+        if ((int64_t)plan->bank->scales.size() > INT64_MAX / K)
+            return fail(CWT_ERR_INVALID_ARG, "output size overflows int64");
+        return launch_one(plan, plan->cfg, x, len, out, (hipStream_t)stream);
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+cwt_status cwt_batch_create(int32_t max_clips, cwt_batch_t* batch_out) {
+    try {
+        if (!batch_out) return fail(CWT_ERR_INVALID_ARG, "batch_out is NULL");
+        if (max_clips < 1 || max_clips > (1 << 20)) return fail(CWT_ERR_INVALID_ARG, "max_clips must be in [1, 2^20]");
+        auto b = std::make_unique<cwt_batch_s>();
+        cwt_status st = batch_init(b.get(), max_clips);
+        if (st != CWT_OK) return st;
+        *batch_out = b.release();
+        return CWT_OK;
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+cwt_status cwt_batch_destroy(cwt_batch_t batch) {
+    if (!batch) return CWT_OK;
+    delete batch;
+    return CWT_OK;
+}
+
+cwt_status cwt_batch_execute(cwt_batch_t batch, const cwt_plan_t* plans, const float* const* xs,
+                             const int64_t* lens, float* const* outs, int32_t n, int32_t use_graph,
+                             void* stream) {
+    try {
+        if (!batch) return fail(CWT_ERR_INVALID_ARG, "NULL batch");
+        std::lock_guard<std::mutex> lk(batch->mu);
+        return batch_run(batch, plans, xs, lens, outs, n, use_graph, (hipStream_t)stream);
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs, const int64_t* lens,
+                             float* const* outs, int32_t n, void* stream) {
+    try {
+        if (n < 0) return fail(CWT_ERR_INVALID_ARG, "n < 0");
+        if (n == 0) return CWT_OK;
+        if (!plans || !plans[0]) return fail(CWT_ERR_INVALID_ARG, "NULL plans");
+        int dev = 0;
+        cwt_status st = current_device(&dev, nullptr);
+        if (st != CWT_OK) return st;
+        auto key = std::make_pair(dev, stream);
+        cwt_batch_s*& slot = t_batches[key];
+        if (!slot || slot->max_clips < n) {
+            int cap = 64;
+            while (cap < n) cap *= 2;
+            auto b = std::make_unique<cwt_batch_s>();
+            st = batch_init(b.get(), cap);
+            if (st != CWT_OK) return st;
+            delete slot;   // its last replay has completed once a new context is needed
+            slot = b.release();
+        }
+        std::lock_guard<std::mutex> lk(slot->mu);
+        return batch_run(slot, plans, xs, lens, outs, n, 1, (hipStream_t)stream);
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t cwt_plan_config(cwt_plan_t plan) { return plan ? plan->cfg : -1; }
+int32_t cwt_plan_num_configs(cwt_plan_t plan) {
+    if (!plan) return -1;
+    return plan->dt == DT_FP32 ? 1 : kNumMfmaCfgs;
+}
+
+cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index) {
+    if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+    if (!cfg_fits(plan, index, plan->hop)) return fail(CWT_ERR_INVALID_ARG, "configuration does not fit this plan");
+    plan->cfg = index;
+    return CWT_OK;
+}
+
+cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out) {
+    try {
+        if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+        if (len < 1) return fail(CWT_ERR_INVALID_ARG, "len must be >= 1");
+        const int64_t K = (len + plan->hop - 1) / plan->hop;
+        const int64_t S = (int64_t)plan->bank->scales.size();
+        float *x = nullptr, *out = nullptr;
+        HIP_TRY(hipMalloc(&x, sizeof(float) * len), "autotune input");
+        std::unique_ptr<float, void (*)(float*)> gx(x, [](float* p) { (void)hipFree(p); });
+        HIP_TRY(hipMalloc(&out, sizeof(float) * S * K), "autotune output");
+        std::unique_ptr<float, void (*)(float*)> go(out, [](float* p) { (void)hipFree(p); });
+        HIP_TRY(hipMemset(x, 0, sizeof(float) * len), "autotune input init");
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0), "event");
+        HIP_TRY(hipEventCreate(&e1), "event");
+        int best = plan->cfg;
+        float best_ms = 1e30f;
+        const int ncfg = cwt_plan_num_configs(plan);
+        for (int c = 0; c < ncfg; ++c) {
+            if (!cfg_fits(plan, c, plan->hop)) continue;
+            for (int w = 0; w < 2; ++w) {
+                cwt_status st = launch_one(plan, c, x, len, out, 0);
+                if (st != CWT_OK) return st;
+            }
+            const int reps = 10;
+            HIP_TRY(hipEventRecord(e0, 0), "event");
+            for (int r = 0; r < reps; ++r) {
+                cwt_status st = launch_one(plan, c, x, len, out, 0);
+                if (st != CWT_OK) return st;
+            }
+            HIP_TRY(hipEventRecord(e1, 0), "event");
+            HIP_TRY(hipEventSynchronize(e1), "event");
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        plan->cfg = best;
+        if (chosen_out) *chosen_out = best;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto m = read_tune_cache();
+        m[tune_key(plan, len)] = best;
+        m[tune_key(plan, 160000)] = best;
+        write_tune_cache(m);
+        return CWT_OK;
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+cwt_status cwt_plan_bank_taps(cwt_plan_t plan, int32_t scale_index, double* taps_out, int64_t cap) {
+    if (!plan || !taps_out) return fail(CWT_ERR_INVALID_ARG, "NULL argument");
+    const Bank& bk = *plan->bank;
+    if (scale_index < 0 || scale_index >= (int)bk.scales.size()) return fail(CWT_ERR_INVALID_ARG, "scale_index out of range");
+    const int pos = bk.caller_to_sorted[scale_index];
+    const int M = bk.M_sorted[pos];
+    if (cap < 2 * (int64_t)M + 1) return fail(CWT_ERR_INVALID_ARG, "taps_out too small");
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * (2 * M + 1)), "readback buffer");
+    std::unique_ptr<double, void (*)(double*)> gd(d, [](double* p) { (void)hipFree(p); });
+    HIP_TRY(decode_bank_taps(plan->dt, bk.d_frags, bk.d_blocks, bk.d_dtaps, bk.d_dgroups, pos, M, d, 0), "bank decode");
+    HIP_TRY(hipMemcpy(taps_out, d, sizeof(double) * (2 * M + 1), hipMemcpyDeviceToHost), "bank readback");
+    return CWT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""ctypes binding of libcwth (include/cwt.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  Importing this
+module loads libcwth.so and raises ImportError if it has not been built
+(``python -c "import __graft_entry__ as g; g.build()"``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcwth.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libcwth.so is not built (%s); run paper_2408_14302_amd/build.py" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c_plan = ctypes.c_void_p
+_i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+_SIGS = {
+    "cwt_plan_create": (_i32, [_dbl, _i32, _vp, _i32, _i32, _i32, ctypes.POINTER(_c_plan)]),
+    "cwt_plan_set_output": (_i32, [_c_plan, _i32]),
+    "cwt_plan_destroy": (_i32, [_c_plan]),
+    "cwt_num_frames": (_i64, [_c_plan, _i64]),
+    "cwt_plan_num_scales": (_i32, [_c_plan]),
+    "cwt_plan_hop": (_i32, [_c_plan]),
+    "cwt_scale_frequencies": (_i32, [_c_plan, _vp]),
+    "cwt_execute": (_i32, [_c_plan, _vp, _i64, _vp, _vp]),
+    "cwt_execute_batch": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "cwt_batch_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "cwt_batch_destroy": (_i32, [_vp]),
+    "cwt_batch_execute": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp]),
+    "cwt_autotune": (_i32, [_c_plan, _i64, ctypes.POINTER(_i32)]),
+    "cwt_plan_config": (_i32, [_c_plan]),
+    "cwt_plan_num_configs": (_i32, [_c_plan]),
+    "cwt_plan_set_config": (_i32, [_c_plan, _i32]),
+    "cwt_plan_bank_taps": (_i32, [_c_plan, _i32, _vp, _i64]),
+    "cwt_status_string": (ctypes.c_char_p, [_i32]),
+    "cwt_last_error": (ctypes.c_char_p, []),
+    "cwt_version": (ctypes.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+OK, INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE, INTERNAL = range(6)
+DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp8": 4}
+MORLET = 0
+
+
+class CwtError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        name = _lib.cwt_status_string(self.status).decode()
+        msg = _lib.cwt_last_error().decode()
+        super().__init__("%s: %s (%s)" % (where, name, msg))
+
+
+def _check(st: int, where: str) -> None:
+    if st != OK:
+        raise CwtError(st, where)
+
+
+def version() -> str:
+    return _lib.cwt_version().decode()
+
+
+def status_string(st: int) -> str:
+    return _lib.cwt_status_string(int(st)).decode()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check_signal(x):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32:
+        raise TypeError("x must be a float32 CUDA tensor")
+    if x.dim() != 1 or not x.is_contiguous():
+        raise ValueError("x must be 1-D and contiguous")
+
+
+class Plan:
+    """A resident plan: scales (samples), hop, operand dtype and output mode.
+
+    ``plan(x)`` returns the scalogram |W| (or signed W) as a [n_scales, K]
+    float32 tensor on x's device, K = ceil(len(x) / hop)."""
+
+    def __init__(self, fs: float, scales: Sequence[float], hop: int, dtype: str = "bf16",
+                 signed: bool = False):
+        sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64).reshape(-1))
+        if dtype not in DTYPES:
+            raise ValueError("dtype must be one of %s" % sorted(DTYPES))
+        h = _c_plan()
+        _check(_lib.cwt_plan_create(float(fs), MORLET, sc.ctypes.data_as(_vp), int(sc.size), int(hop),
+                                    DTYPES[dtype], ctypes.byref(h)), "cwt_plan_create")
+        self._h = h
+        self.fs = float(fs)
+        self.scales = sc.copy()
+        self.hop = int(hop)
+        self.dtype = dtype
+        self.signed = bool(signed)
+        if signed:
+            _check(_lib.cwt_plan_set_output(self._h, 1), "cwt_plan_set_output")
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_scales(self) -> int:
+        return int(_lib.cwt_plan_num_scales(self._h))
+
+    def num_frames(self, n: int) -> int:
+        return int(_lib.cwt_num_frames(self._h, int(n)))
+
+    def set_signed(self, signed: bool) -> None:
+        _check(_lib.cwt_plan_set_output(self._h, 1 if signed else 0), "cwt_plan_set_output")
+        self.signed = bool(signed)
+
+    def frequencies(self) -> np.ndarray:
+        hz = np.zeros(self.num_scales, dtype=np.float64)
+        _check(_lib.cwt_scale_frequencies(self._h, hz.ctypes.data_as(_vp)), "cwt_scale_frequencies")
+        return hz
+
+    def bank_taps(self, i: int) -> np.ndarray:
+        M = int(np.floor(8.0 * self.scales[i]))
+        t = np.zeros(2 * M + 1, dtype=np.float64)
+        _check(_lib.cwt_plan_bank_taps(self._h, int(i), t.ctypes.data_as(_vp), t.size), "cwt_plan_bank_taps")
+        return t
+
+    @property
+    def config(self) -> int:
+        return int(_lib.cwt_plan_config(self._h))
+
+    @property
+    def num_configs(self) -> int:
+        return int(_lib.cwt_plan_num_configs(self._h))
+
+    def set_config(self, i: int) -> None:
+        _check(_lib.cwt_plan_set_config(self._h, int(i)), "cwt_plan_set_config")
+
+    def autotune(self, n: int) -> int:
+        c = _i32()
+        _check(_lib.cwt_autotune(self._h, int(n), ctypes.byref(c)), "cwt_autotune")
+        return int(c.value)
+
+    def output(self, n: int, device=None):
+        import torch
+        return torch.empty((self.num_scales, self.num_frames(n)), dtype=torch.float32, device=device)
+
+    def execute(self, x, out, stream=None) -> None:
+        """Queue the transform of x into out (both CUDA tensors) on `stream`."""
+        _check_signal(x)
+        n = x.numel()
+        if out.dtype.itemsize != 4 or not out.is_contiguous() or out.numel() != self.num_scales * self.num_frames(n):
+            raise ValueError("out must be a contiguous float32 tensor of n_scales * K elements")
+        _check(_lib.cwt_execute(self._h, x.data_ptr() if n else None, n, out.data_ptr() if n else None,
+                                _stream_ptr(stream)), "cwt_execute")
+
+    def __call__(self, x, out=None, stream=None):
+        if out is None:
+            out = self.output(x.numel(), device=x.device)
+        self.execute(x, out, stream)
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.cwt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _arrays(plans, xs, outs):
+    n = len(plans)
+    if not (len(xs) == len(outs) == n):
+        raise ValueError("plans, xs and outs differ in length")
+    P = (_vp * n)(*[p.handle.value for p in plans])
+    X = (_vp * n)(*[x.data_ptr() if x.numel() else None for x in xs])
+    L = (_i64 * n)(*[x.numel() for x in xs])
+    O = (_vp * n)(*[o.data_ptr() if o.numel() else None for o in outs])
+    return n, P, X, L, O
+
+
+def _outs_for(plans, xs):
+    import torch
+    return [torch.empty((p.num_scales, p.num_frames(x.numel())), dtype=torch.float32, device=x.device)
+            for p, x in zip(plans, xs)]
+
+
+def execute_batch(plans, xs, outs=None, stream=None):
+    """All clips in one persistent launch (library-owned batch context)."""
+    for x in xs:
+        _check_signal(x)
+    if outs is None:
+        outs = _outs_for(plans, xs)
+    n, P, X, L, O = _arrays(plans, xs, outs)
+    _check(_lib.cwt_execute_batch(P, X, L, O, n, _stream_ptr(stream)), "cwt_execute_batch")
+    return outs
+
+
+class Batch:
+    """Explicit batch context (pinned descriptors + captured HIP graph)."""
+
+    def __init__(self, max_clips: int):
+        h = _vp()
+        _check(_lib.cwt_batch_create(int(max_clips), ctypes.byref(h)), "cwt_batch_create")
+        self._h = h
+        self.max_clips = int(max_clips)
+
+    def __call__(self, plans, xs, outs=None, stream=None, graph: bool = True):
+        for x in xs:
+            _check_signal(x)
+        if outs is None:
+            outs = _outs_for(plans, xs)
+        n, P, X, L, O = _arrays(plans, xs, outs)
+        _check(_lib.cwt_batch_execute(self._h, P, X, L, O, n, 1 if graph else 0, _stream_ptr(stream)),
+               "cwt_batch_execute")
+        return outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.cwt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def raw():
+    """The ctypes library object (for ABI-level tests)."""
+    return _lib

@@ -1,0 +1,407 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every case prints rel-L2 and max-abs against the oracle beside its tolerance.
+Inputs are the seeded synthetic clips (tone + pink noise, peak-normalised).
+"""
+import ctypes
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import DTYPES, TOL, assert_close, errors, torch_cuda
+from paper_2408_14302_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_cuda()
+
+
+@pytest.fixture(scope="module")
+def cw():
+    from paper_2408_14302_amd import cwth
+    return cwth
+
+
+def gpu_run(torch, plan, x):
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    out = plan(xd)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@functools.lru_cache(maxsize=64)
+def clip(config, index, n, snr):
+    return synth.make_clip(synth.clip_seed(config, index), n, 16000.0, snr)
+
+
+@functools.lru_cache(maxsize=32)
+def oracle_full(config, index, n, snr, nscales, hop):
+    x = clip(config, index, n, snr).astype(np.float64)
+    return oracle.cwt(x, np.arange(1, nscales + 1, dtype=np.float64), hop)
+
+
+# ---------------------------------------------------------------------------
+# Wavelet bank: the stored operand values against the FP64 taps rounded once.
+
+def _e4m3_table():
+    vals = []
+    for code in range(0x7F):  # positive finite codes (0x7F is NaN)
+        e, m = code >> 3, code & 7
+        vals.append(m * 2.0 ** -9 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7))
+    return np.array(vals)
+
+
+def _round_e4m3(v):
+    """Nearest e4m3 value (ties to even code), saturating at 448."""
+    tab = _e4m3_table()
+    a = np.minimum(np.abs(v), 448.0)
+    d = np.abs(a[:, None] - tab[None, :])
+    best = d.min(axis=1, keepdims=True)
+    cand = d == best
+    codes = np.arange(tab.size)[None, :]
+    even = cand & (codes % 2 == 0)
+    pick = np.where(even.any(axis=1), np.argmax(even, axis=1), np.argmax(cand, axis=1))
+    return np.sign(v) * tab[pick]
+
+
+def _round_bf16(v):
+    """RNE of float64 to bfloat16 by integer arithmetic on the IEEE bits."""
+    b = np.asarray(v, dtype=np.float64).view(np.uint64)
+    keep = b >> np.uint64(45)
+    rem = b & np.uint64((1 << 45) - 1)
+    half = np.uint64(1 << 44)
+    up = (rem > half) | ((rem == half) & ((keep & np.uint64(1)) == np.uint64(1)))
+    keep = keep + up.astype(np.uint64)
+    return (keep << np.uint64(45)).view(np.float64)
+
+
+def _expected_bank(dt, t, alpha=None):
+    if dt == "fp32":
+        return t.astype(np.float32).astype(np.float64)
+    if dt == "fp16":
+        return t.astype(np.float16).astype(np.float64)
+    if dt == "bf16":
+        return _round_bf16(t)
+    if dt == "bf16x3":
+        hi = _round_bf16(t)
+        return hi + _round_bf16(t - hi)
+    return _round_e4m3(t * alpha) / alpha
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_bank_matches_fp64_taps(torch, cw, dt):
+    scales = [0.1, 1.0, 2.5, 7.3, 32.0, 128.0, 77.7, 300.0]
+    plan = cw.Plan(16000.0, scales, 1, dt)
+    for i, s in enumerate(scales):
+        t = oracle.taps(s)
+        got = plan.bank_taps(i)
+        alpha = None
+        if dt == "fp8":
+            m, e = math.frexp(448.0 * math.sqrt(s))
+            alpha = math.ldexp(1.0, e - 1)
+        exp = _expected_bank(dt, t, alpha)
+        # The device evaluates exp/cos in FP64 too; allow the neighbouring
+        # value only where the FP64 tap sits within 1e-13 (relative) of a
+        # rounding boundary of the operand format.
+        bad = got != exp
+        if bad.any():
+            tt = t[bad]
+            lo = _expected_bank(dt, tt * (1 - 1e-13), alpha)
+            hi = _expected_bank(dt, tt * (1 + 1e-13), alpha)
+            ok = (got[bad] == lo) | (got[bad] == hi)
+            assert ok.all(), (dt, s, np.flatnonzero(bad)[~ok][:5], got[bad][~ok][:5], exp[bad][~ok][:5])
+        print("bank %-6s s=%-6g taps %d mismatches-at-boundary %d" % (dt, s, t.size, int(bad.sum())))
+
+
+# ---------------------------------------------------------------------------
+# The measured configurations.
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("hop", [1, 64])
+def test_one_second_clip_32_scales(torch, cw, dt, hop):
+    """1 s at 16 kHz, linear scales 1..32, hop 1 and 64, SNR 0 dB."""
+    x = clip(1, 0, 16000, 0.0)
+    ref = oracle_full(1, 0, 16000, 0.0, 32, hop)
+    plan = cw.Plan(16000.0, np.arange(1, 33), hop, dt, signed=True)
+    got = gpu_run(torch, plan, x)
+    assert got.shape == ref.shape
+    assert_close(dt, got, ref, "1s/32sc hop=%d" % hop)
+
+
+C2_CASES = [(hop, snr) for hop in (1, 512) for snr in (-6.0, 0.0, 6.0)] + [(32, 0.0), (256, 0.0)]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("hop,snr", C2_CASES)
+def test_ten_second_clip_128_scales(torch, cw, dt, hop, snr):
+    """10 s at 16 kHz (160000 samples), linear scales 1..128 (up to 2049 taps)."""
+    idx = {-6.0: 0, 0.0: 1, 6.0: 2}[snr]
+    x = clip(2, idx, 160000, snr)
+    ref = oracle_full(2, idx, 160000, snr, 128, hop)
+    plan = cw.Plan(16000.0, np.arange(1, 129), hop, dt, signed=True)
+    got = gpu_run(torch, plan, x)
+    assert got.shape == ref.shape == (128, -(-160000 // hop))
+    assert_close(dt, got, ref, "10s/128sc hop=%d snr=%g" % (hop, snr))
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+@pytest.mark.parametrize("hop", [128, 512])
+def test_sixty_second_48k_geometric_sampled(torch, cw, dt, hop):
+    """60 s at 48 kHz (2.88 M samples), 256 geometric scales 1..1024 (up to
+    16385 taps), checked on sampled coefficients the oracle computes one by one."""
+    n = 2_880_000
+    x = synth.make_clip(synth.clip_seed(5, 0), n, 48000.0, 0.0)
+    scales = synth.geometric_scales(256, 1024.0)
+    plan = cw.Plan(48000.0, scales, hop, dt, signed=True)
+    got = gpu_run(torch, plan, x)
+    K = -(-n // hop)
+    assert got.shape == (256, K)
+    rng = np.random.default_rng(hop)
+    ii = rng.integers(0, 256, 3000)
+    kk = rng.integers(0, K, 3000)
+    ii[:8] = [0, 255, 255, 255, 128, 0, 255, 200]
+    kk[:8] = [0, 0, K - 1, 1, K - 1, K - 1, K // 2, 3]
+    ref = oracle.points(x.astype(np.float64), scales, hop, ii, kk)
+    assert_close(dt, got[ii, kk], ref, "60s/48k/256geo hop=%d (3000 samples)" % hop)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases: ragged tails, tiny and huge hops, odd scale sets.
+
+EDGE = [
+    ("one sample", 1, [1.0, 2.0], 1),
+    ("two samples", 2, [0.1, 3.0], 2),
+    ("shorter than taps", 300, [100.0, 1.0], 1),
+    ("hop > len", 50, [1.0, 4.0], 4099),
+    ("hop = len", 4096, [2.0, 9.0], 4096),
+    ("odd hop, 40 scales (2 blocks)", 5000, list(range(1, 41)), 3),
+    ("hop 7, non-integer scales", 7001, list(np.linspace(0.3, 57.1, 37)), 7),
+    ("hop 2", 3333, [1.0, 5.0, 30.0], 2),
+    ("hop 8", 9000, [1.0, 64.0, 33.3], 8),
+    ("hop 16", 9000, [1.0, 64.0, 33.3], 16),
+    ("hop 24", 9000, [1.0, 64.0, 33.3], 24),
+    ("hop 48 (rows staging)", 9000, [1.0, 64.0, 33.3], 48),
+    ("hop 1000", 40000, [1.0, 64.0, 128.0], 1000),
+    ("duplicates, unsorted", 4000, [9.0, 1.0, 9.0, 0.05, 3.0], 5),
+    ("tile tail", 128 * 3 + 5, list(range(1, 9)), 1),
+]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("case", EDGE, ids=[e[0] for e in EDGE])
+def test_edge_cases(torch, cw, dt, case):
+    name, n, scales, hop = case
+    x = synth.make_clip(77 + n, n, 16000.0, 0.0)
+    ref = oracle.cwt(x.astype(np.float64), scales, hop)
+    plan = cw.Plan(16000.0, scales, hop, dt, signed=True)
+    got = gpu_run(torch, plan, x)
+    assert got.shape == ref.shape
+    assert_close(dt, got, ref, name)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8", "fp32"])
+def test_more_than_four_blocks(torch, cw, dt):
+    """200 geometric scales (7 blocks, two work-group groups), hop 96."""
+    n = 50000
+    x = clip(9, 0, n, 0.0)
+    scales = np.geomspace(1.0, 512.0, 200)
+    ref = oracle.cwt(x.astype(np.float64), scales, 96)
+    plan = cw.Plan(16000.0, scales, 96, dt, signed=True)
+    got = gpu_run(torch, plan, x)
+    assert_close(dt, got, ref, "200 scales hop 96")
+
+
+def test_empty_signal_is_noop(torch, cw):
+    plan = cw.Plan(16000.0, [1.0, 2.0], 3, "bf16")
+    out = plan(torch.zeros(0, device="cuda"))
+    assert tuple(out.shape) == (2, 0)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp32", "fp8"])
+def test_magnitude_is_abs_of_signed(torch, cw, dt):
+    x = clip(1, 0, 16000, 0.0)
+    p = cw.Plan(16000.0, np.arange(1, 33), 5, dt, signed=True)
+    xd = torch.from_numpy(x).cuda()
+    w = p(xd)
+    p.set_signed(False)
+    s = p(xd)
+    torch.cuda.synchronize()
+    assert torch.equal(s, w.abs())
+
+
+# ---------------------------------------------------------------------------
+# Closed forms on the device (tone response, impulse) under tolerance.
+
+@pytest.mark.parametrize("dt", ["bf16x3", "fp32"])
+def test_tone_response_on_device(torch, cw, dt):
+    fs, f = 16000.0, 500.0
+    Om = 2 * math.pi * f / fs
+    n = 20000
+    x = np.cos(Om * np.arange(n)).astype(np.float32)
+    scales = np.arange(10, 42, dtype=np.float64)
+    p = cw.Plan(fs, scales, 1, dt, signed=False)
+    S = gpu_run(torch, p, x)
+    amp = S[:, n // 2:n // 2 + 40].max(axis=1)
+    s_star = (5 + math.sqrt(27)) / 2 / Om
+    assert scales[int(np.argmax(amp))] in (math.floor(s_star), math.ceil(s_star))
+    env = np.sqrt(scales) * math.sqrt(math.pi / 2) * (np.exp(-(scales * Om - 5) ** 2 / 2) + np.exp(-(scales * Om + 5) ** 2 / 2))
+    assert np.abs(amp - env).max() < 2e-3 * env.max()
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_impulse_response_on_device(torch, cw, dt):
+    n, n0 = 3000, 1234
+    x = np.zeros(n, dtype=np.float32)
+    x[n0] = 1.0
+    scales = [1.0, 4.0, 25.0, 60.0]
+    for hop in (1, 17):
+        p = cw.Plan(16000.0, scales, hop, dt, signed=True)
+        got = gpu_run(torch, p, x)
+        for i, s in enumerate(scales):
+            exp = p.bank_taps(i)
+            M = (exp.size - 1) // 2
+            row = np.zeros(got.shape[1])
+            for k in range(row.size):
+                d = n0 - k * hop
+                if abs(d) <= M:
+                    row[k] = exp[d + M]
+            # one product per coefficient: exact except for the FP8 descale
+            np.testing.assert_allclose(got[i], row, rtol=1e-6, atol=1e-30)
+
+
+# ---------------------------------------------------------------------------
+# Determinism: the summation order is fixed, so results are bit-identical
+# run to run and across kernel configurations.
+
+@pytest.mark.parametrize("dt", ["bf16", "fp16", "bf16x3", "fp32"])
+def test_bitwise_repeatable_and_config_independent(torch, cw, dt):
+    x = clip(2, 1, 160000, 0.0)
+    xd = torch.from_numpy(x).cuda()
+    for hop in (1, 3, 256):
+        p = cw.Plan(16000.0, np.arange(1, 129), hop, dt, signed=True)
+        a = p(xd)
+        b = p(xd)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        for c in range(p.num_configs):
+            try:
+                p.set_config(c)
+            except cw.CwtError:
+                continue
+            assert torch.equal(p(xd), a), (dt, hop, c)
+
+
+# ---------------------------------------------------------------------------
+# Batching: one persistent launch, bit-identical to the clips run alone.
+
+def _batch_inputs(torch, seed, count, hops, lo=2000, hi=60000):
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(lo, hi, count)
+    hs = rng.choice(hops, count)
+    xs = [torch.from_numpy(synth.make_clip(seed * 1000 + i, int(n), 16000.0, float(rng.uniform(-6, 6)))).cuda()
+          for i, n in enumerate(lens)]
+    return xs, [int(h) for h in hs]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp16", "bf16x3", "fp8"])
+def test_batch_bitwise_equals_single(torch, cw, dt):
+    xs, hs = _batch_inputs(torch, 3, 24, [1, 3, 64, 256, 512])
+    xs.append(torch.zeros(0, device="cuda"))
+    hs.append(64)
+    scales = np.arange(1, 129)
+    plans = {h: cw.Plan(16000.0, scales, h, dt, signed=True) for h in set(hs)}
+    pl = [plans[h] for h in hs]
+    alone = [p(x) for p, x in zip(pl, xs)]
+    outs = cw.execute_batch(pl, xs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(alone, outs)):
+        assert torch.equal(a, b), (dt, i, hs[i], xs[i].numel())
+
+
+def test_batch_graph_replays(torch, cw):
+    scales = np.arange(1, 129)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (64, 256, 512)}
+    B = cw.Batch(64)
+    for rep, (seed, count) in enumerate([(5, 40), (6, 40), (7, 9), (8, 40)]):
+        xs, hs = _batch_inputs(torch, seed, count, [64, 256, 512])
+        pl = [plans[h] for h in hs]
+        alone = [p(x) for p, x in zip(pl, xs)]
+        g = B(pl, xs, graph=True)
+        ng = B(pl, xs, graph=False)
+        torch.cuda.synchronize()
+        for a, b, c in zip(alone, g, ng):
+            assert torch.equal(a, b) and torch.equal(a, c), rep
+
+
+def test_batch_against_oracle(torch, cw):
+    xs, hs = _batch_inputs(torch, 11, 6, [64, 256, 512], lo=16000, hi=40000)
+    scales = np.arange(1, 129)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16", signed=True) for h in set(hs)}
+    outs = cw.execute_batch([plans[h] for h in hs], xs)
+    torch.cuda.synchronize()
+    for x, h, o in zip(xs, hs, outs):
+        ref = oracle.cwt(x.cpu().numpy().astype(np.float64), scales, h)
+        assert_close("bf16", o.cpu().numpy(), ref, "batch hop=%d" % h)
+
+
+def test_batch_rejects_mixed_plans(torch, cw):
+    a = cw.Plan(16000.0, [1.0, 2.0], 4, "bf16")
+    b = cw.Plan(16000.0, [1.0, 3.0], 4, "bf16")
+    c = cw.Plan(16000.0, [1.0, 2.0], 4, "fp16")
+    x = torch.zeros(100, device="cuda")
+    for other in (b, c):
+        with pytest.raises(cw.CwtError) as e:
+            cw.execute_batch([a, other], [x, x])
+        assert e.value.status == cw.UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# ABI argument checks with a device present.
+
+def test_invalid_arguments(torch, cw):
+    lib = cw.raw()
+    h = ctypes.c_void_p()
+    sc = (ctypes.c_double * 2)(1.0, 2.0)
+    bad = (ctypes.c_double * 2)(1.0, -2.0)
+    nan = (ctypes.c_double * 1)(float("nan"))
+    assert lib.cwt_plan_create(16000.0, 0, sc, 2, 0, 1, ctypes.byref(h)) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(16000.0, 0, bad, 2, 1, 1, ctypes.byref(h)) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(16000.0, 0, nan, 1, 1, 1, ctypes.byref(h)) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(16000.0, 0, sc, 0, 1, 1, ctypes.byref(h)) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(0.0, 0, sc, 2, 1, 1, ctypes.byref(h)) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(16000.0, 0, None, 2, 1, 1, ctypes.byref(h)) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(16000.0, 0, sc, 2, 1, 1, None) == cw.INVALID_ARG
+    assert lib.cwt_plan_create(16000.0, 3, sc, 2, 1, 1, ctypes.byref(h)) == cw.UNSUPPORTED
+    assert lib.cwt_plan_create(16000.0, 0, sc, 2, 1, 9, ctypes.byref(h)) == cw.UNSUPPORTED
+    assert lib.cwt_plan_create(16000.0, 0, sc, 2, 3, 1, ctypes.byref(h)) == cw.OK
+    x = torch.zeros(10, device="cuda")
+    o = torch.zeros(2 * 4, device="cuda")
+    assert lib.cwt_execute(h, x.data_ptr(), -1, o.data_ptr(), None) == cw.INVALID_ARG
+    assert lib.cwt_execute(h, None, 10, o.data_ptr(), None) == cw.INVALID_ARG
+    assert lib.cwt_execute(h, x.data_ptr(), 10, None, None) == cw.INVALID_ARG
+    assert lib.cwt_execute(h, None, 0, None, None) == cw.OK
+    assert lib.cwt_execute(None, x.data_ptr(), 10, o.data_ptr(), None) == cw.INVALID_ARG
+    assert lib.cwt_num_frames(h, 10) == 4 and lib.cwt_num_frames(h, -1) == -1
+    assert lib.cwt_execute(h, x.data_ptr(), 10, o.data_ptr(), None) == cw.OK
+    torch.cuda.synchronize()
+    assert lib.cwt_plan_destroy(h) == cw.OK
+    assert lib.cwt_plan_destroy(None) == cw.OK
+
+
+def test_frequencies_and_autotune(torch, cw):
+    p = cw.Plan(16000.0, [1.0, 5.0, 100.0], 32, "bf16")
+    hz = p.frequencies()
+    np.testing.assert_allclose(hz, 5 / (2 * math.pi) * 16000.0 / np.array([1.0, 5.0, 100.0]), rtol=1e-15)
+    x = torch.from_numpy(clip(1, 0, 16000, 0.0)).cuda()
+    before = p(x)
+    c = p.autotune(16000)
+    assert 0 <= c < p.num_configs and p.config == c
+    after = p(x)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
