@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the hop-strided Morlet CWT on one MI355X.
+
+Workload (the headline): 10 s clips at 16 kHz (160000 samples), 128 linear
+Morlet scales s = 1..128 (up to 2049 taps), three clips per step at SNR -6/0/6
+dB, hop 1 (the full CWT), BF16 operands on the matrix cores with FP32
+accumulation, |W| written as FP32 [scale][frame].  `value` is coefficients per
+second over the timed steps, inputs resident in HBM, outputs rotated over two
+sets larger than the 256 MB Infinity Cache.
+
+The same JSON line carries the other legs of the metric: the plain FP32 kernel
+at hop 1, both paths at hop 512 (256 clips per persistent launch), their
+ratios, the roofline of the dominant kernel, the serving session's p50/p99 at a
+fixed Poisson arrival rate, and the FP64 CPU oracle as a timed baseline.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FS = 16000.0
+N = 160000
+S = 128
+METRIC = "CWT coeffs/sec at hop 1 & 512, BF16-MFMA vs FP32 plain; serving p50/p99 ms"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch512", type=int, default=256, help="clips per hop-512 launch")
+    ap.add_argument("--qps", type=float, default=2000.0, help="serving arrival rate")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["bf16-hop1", "fp32-hop1", "bf16-hop512", "fp32-hop512"], default=None,
+                    help="time one leg only (for profiling runs)")
+    return ap.parse_args()
+
+
+def alg_flops_per_coeff(scales):
+    """2 L_i flop per coefficient, L_i = 2 floor(8 s_i) + 1 (Eq. (1), one tap per sample)."""
+    L = 2 * np.floor(8.0 * np.asarray(scales, dtype=np.float64)) + 1
+    return 2.0 * L
+
+
+def time_launches(torch, launch, nsets, steps, warmup):
+    """launch(step_index) queues one step; returns (total_ms, [per-step ms])."""
+    st = torch.cuda.current_stream()
+    for w in range(warmup):
+        launch(w)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(st)
+    for s in range(steps):
+        ev[s][0].record(st)
+        launch(s)
+        ev[s][1].record(st)
+    t1.record(st)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1), [a.elapsed_time(b) for a, b in ev]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        msg = ("bench.py measures one GPU: this build runs the transform on a single MI355X "
+               "(the work shards by clip with no collective; see DESIGN.md). Run with --gpus 1.")
+        print(msg, file=sys.stderr)
+        print(json.dumps({"metric": METRIC, "error": msg, "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2408_14302_amd import cwth, serve, synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    scales = synth.linear_scales(S)
+    fpc = alg_flops_per_coeff(scales)
+    flops_per_frame = float(fpc.sum())                  # all scales, one frame
+
+    # ---------------- inputs (resident) ----------------
+    clips = [torch.from_numpy(synth.make_clip(synth.clip_seed(2, i), N, FS, snr)).to(dev)
+             for i, snr in enumerate((-6.0, 0.0, 6.0))]
+    K1 = N
+    out1 = [[torch.empty((S, K1), dtype=torch.float32, device=dev) for _ in clips] for _ in range(2)]
+    result = {}
+    stream = torch.cuda.current_stream()
+
+    def leg_hop1(dt):
+        plan = cwth.Plan(FS, scales, 1, dt)
+        def launch(s):
+            o = out1[s % 2]
+            for c, x in enumerate(clips):
+                plan.execute(x, o[c], stream)
+        steps = args.steps if dt == "bf16" else max(5, args.steps // 5)
+        total, per = time_launches(torch, launch, 2, steps, args.warmup)
+        ms = total / steps
+        coeffs = len(clips) * S * K1
+        # per-kernel duration: one launch per clip inside each step
+        per_launch_ms = float(np.mean(per)) / len(clips)
+        return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": per_launch_ms,
+                "steps": steps, "config": plan.config}
+
+    # hop 512: many clips per launch (one clip alone is ~0.1 us of work)
+    nb = args.batch512
+    K512 = -(-N // 512)
+
+    def leg_hop512(dt):
+        base = [synth.make_clip(synth.clip_seed(2, 10 + i), N, FS, float(np.linspace(-6, 6, 16)[i])) for i in range(16)]
+        base = [torch.from_numpy(b).to(dev) for b in base]
+        sets = [[base[(j * 7 + k) % 16].clone() for k in range(nb)] for j in range(2)]
+        outs = [[torch.empty((S, K512), dtype=torch.float32, device=dev) for _ in range(nb)] for _ in range(2)]
+        plan = cwth.Plan(FS, scales, 512, dt)
+        plans = [plan] * nb
+        B = cwth.Batch(nb)
+
+        def launch(s):
+            B(plans, sets[s % 2], outs[s % 2], stream=stream, graph=True)
+        steps = args.steps if dt == "bf16" else max(5, args.steps // 5)
+        total, per = time_launches(torch, launch, 2, steps, args.warmup)
+        ms = total / steps
+        coeffs = nb * S * K512
+        return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": float(np.mean(per)),
+                "clips_per_launch": nb, "steps": steps}
+
+    legs = [("bf16", 1), ("fp32", 1), ("bf16", 512), ("fp32", 512)]
+    if args.only:
+        d, h = args.only.split("-hop")
+        legs = [(d, int(h))]
+    for dt, hop in legs:
+        log("leg %s hop %d ..." % (dt, hop))
+        r = leg_hop1(dt) if hop == 1 else leg_hop512(dt)
+        result[(dt, hop)] = r
+        log("  %s hop %d: %.3f ms/step, %.3e coeffs/s" % (dt, hop, r["ms_per_step"], r["coeffs_per_s"]))
+
+    head = result.get(("bf16", 1)) or next(iter(result.values()))
+    line = {
+        "metric": METRIC,
+        "value": head["coeffs_per_s"],
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "10 s clips at 16 kHz (160000 samples), 128 linear Morlet scales 1..128, "
+                               "hop 1, 3 clips per step (SNR -6/0/6 dB), |W| as FP32",
+                   "clip_samples": N, "fs_hz": FS, "n_scales": S, "hop": 1, "clips_per_step": len(clips),
+                   "operands": "bf16 (MFMA, FP32 accumulation)"},
+    }
+    legs_out = {}
+    for (dt, hop), r in result.items():
+        legs_out["%s_hop%d" % (dt, hop)] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+    for hop in (1, 512):
+        if ("bf16", hop) in result and ("fp32", hop) in result:
+            legs_out["ratio_bf16_over_fp32_hop%d" % hop] = result[("bf16", hop)]["coeffs_per_s"] / result[("fp32", hop)]["coeffs_per_s"]
+    line["legs"] = legs_out
+
+    # ---------------- roofline of the dominant kernel ----------------
+    if ("bf16", 1) in result:
+        r = result[("bf16", 1)]
+        flops = flops_per_frame * K1                      # one launch = one clip
+        ach = flops / (r["per_launch_ms"] * 1e-3) / 1e12
+        line["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                            "frac": ach / PEAK_BF16_TFLOPS, "traffic": None,
+                            "kernel": "k_mfma_grid<bf16> hop 1, one 160000-sample clip x 128 scales",
+                            "alg_flop_per_launch": flops, "avg_launch_ms": r["per_launch_ms"]}
+    if ("bf16", 512) in result:
+        r = result[("bf16", 512)]
+        byt = nb * (4.0 * N + 4.0 * S * K512)
+        gbs = byt / (r["per_launch_ms"] * 1e-3) / 1e9
+        line["roofline_hop512"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": gbs / PEAK_HBM_GBS, "alg_bytes_per_launch": byt,
+                                   "kernel": "k_mfma_persistent<bf16> hop 512, %d clips" % nb}
+
+    # ---------------- serving ----------------
+    if not args.no_serve and not args.only:
+        log("serving session: %.0f QPS for %.1f s ..." % (args.qps, args.serve_seconds))
+        lens = synth.serving_lengths(1430400, 48)
+        sclips = [torch.from_numpy(synth.make_clip(1430500 + i, int(n), FS, 0.0)).to(dev) for i, n in enumerate(lens)]
+        plans = {(s_, h): cwth.Plan(FS, synth.linear_scales(s_), h, "bf16") for s_ in (64, 128) for h in (1, 256, 512)}
+        ex = serve.GpuExecutor(3, max_clips=64)
+        # warm every plan and captured-graph shape once, untimed
+        serve.serve_session(400.0, 1.0, sclips, plans, seed=7, executor=ex)
+        stats, reqs = serve.serve_session(args.qps, args.serve_seconds, sclips, plans, seed=1430401, executor=ex)
+        sm = stats.summary()
+        sm["qps_offered"] = args.qps
+        sm["budget_bytes"] = 4 << 30
+        sm["slots"] = 3
+        line["serving"] = sm
+        log("  serving: p50 %.3f ms p99 %.3f ms" % (sm.get("p50_ms", float("nan")), sm.get("p99_ms", float("nan"))))
+
+    # ---------------- CPU baseline (FP64 oracle) ----------------
+    if not args.no_cpu and not args.only:
+        import oracle
+        xs = [c.cpu().numpy().astype(np.float64) for c in clips]
+        cores = oracle.max_threads()
+        log("cpu baseline: FP64 oracle on %d threads ..." % cores)
+        t = time.perf_counter()
+        for x in xs:
+            oracle.cwt(x, scales, 1)
+        dt_s = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": len(xs) * S * N / dt_s, "unit": "coeffs/s", "cores": cores,
+                                "kind": "oracle", "seconds": dt_s,
+                                "sample": "the full step: 3 clips x 160000 samples x 128 scales at hop 1, FP64"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -111,6 +111,8 @@ struct DirectArgs {
 
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
+hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, const int32_t* d_prefix,
+                               int nclips, int total_tiles, hipStream_t s);
 // cfgA = frame blocks per wave (1, 2, 4); nb = blocks per group bound (1, 2, 4).
 hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,
                        int grid, hipStream_t s);

@@ -388,7 +388,7 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
 }
 
 static int default_cfg(int dt, int hop) {
-    if (dt == DT_FP32) return 0;
+    if (dt == DT_FP32 || dt == DT_FP8) return 0;
     return hop <= 64 ? 1 : 0;   // {2,8} for small hops, {1,8} otherwise
 }
 
@@ -397,6 +397,9 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
     const MfmaCfg& c = kMfmaCfgs[cfg];
     if (c.A == 4 && p->bank->nb_max > 2) return false;   // register budget
+    // FP8 scales the signal per 128-frame tile; a fixed tile keeps every clip's
+    // result independent of the configuration and of the batch it runs in.
+    if (p->dt == DT_FP8 && c.A != 1) return false;
     Staging s = staging_for(p->dt, hop, 128 * c.A, c.chunk);
     return 2 * s.bytes <= mfma_max_lds_bytes() - 2048;
 }
@@ -554,26 +557,22 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
     const Bank& bk = *p0->bank;
 
-    if (p0->dt == DT_FP32) {
-        // The plain path has no persistent kernel: one launch per clip.
-        for (int i = 0; i < n; ++i) {
-            if (lens[i] == 0) continue;
-            cwt_status st = launch_one(plans[i], 0, xs[i], lens[i], outs[i], stream);
-            if (st != CWT_OK) return st;
-        }
-        return CWT_OK;
-    }
-    // One configuration for the whole launch: the first plan's, shrunk until
-    // every clip's staging buffer fits.
+    // One configuration for the whole launch: the first plan's, moved on until
+    // every clip's staging buffer fits.  (FP32 has a single configuration.)
+    const bool fp32 = p0->dt == DT_FP32;
     int cfg = p0->cfg;
-    for (int tries = 0; tries < kNumMfmaCfgs; ++tries) {
-        bool ok = true;
-        for (int i = 0; i < n && ok; ++i) ok = cfg_fits(plans[i], cfg, plans[i]->hop);
-        if (ok) break;
-        cfg = (cfg + 1) % kNumMfmaCfgs;
+    if (!fp32) {
+        for (int tries = 0; tries < kNumMfmaCfgs; ++tries) {
+            bool ok = true;
+            for (int i = 0; i < n && ok; ++i) ok = cfg_fits(plans[i], cfg, plans[i]->hop);
+            if (ok) break;
+            cfg = (cfg + 1) % kNumMfmaCfgs;
+        }
     }
-    const MfmaCfg& c = kMfmaCfgs[cfg];
-    const int F = 128 * c.A;
+    const MfmaCfg c = fp32 ? MfmaCfg{1, 1} : kMfmaCfgs[cfg];
+    const int F = fp32 ? kDirectFrames : 128 * c.A;
+    const int64_t groups_per_tile = fp32 ? ((int64_t)bk.dgroups.size() + kDirectWaves - 1) / kDirectWaves
+                                         : (int64_t)bk.groups.size();
 
     // Wait until the pinned buffer we are about to overwrite has been consumed.
     const int slot = b->flip;
@@ -600,7 +599,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     for (int j = 0; j < nc; ++j) {
         hc[j] = clips[order[j]];
         hp[j] = (int32_t)total;
-        total += (int64_t)clips[order[j]].ntile * (int64_t)bk.groups.size();
+        total += (int64_t)clips[order[j]].ntile * groups_per_tile;
         if (total > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "batch has too many tiles");
     }
     hp[nc] = (int32_t)total;
@@ -608,6 +607,22 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     ((int32_t*)host)[1] = (int32_t)total;
     const size_t used_bytes = 16 + sizeof(ClipArg) * nc + sizeof(int32_t) * (nc + 1);
 
+    if (fp32) {
+        // The plain path: descriptor upload and one flat launch over every tile.
+        DirectArgs d;
+        std::memset(&d, 0, sizeof(d));
+        d.taps = bk.d_dtaps;
+        d.groups = bk.d_dgroups;
+        d.ngroups = (int)bk.dgroups.size();
+        d.signed_out = p0->signed_out;
+        HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
+        HIP_TRY(launch_direct_batch(d, (const ClipArg*)(b->d_desc + 16),
+                                    (const int32_t*)(b->d_desc + 16 + sizeof(ClipArg) * nc), nc, (int)total,
+                                    stream), "direct batch launch");
+        HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
+        b->used[slot] = true;
+        return CWT_OK;
+    }
     MfmaArgs a;
     std::memset(&a, 0, sizeof(a));
     a.frags = bk.d_frags;

@@ -20,14 +20,10 @@ __device__ __forceinline__ int xcd_remap_d(int id, int n) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-__global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
-    __shared__ float X[kDirectChunk * kRowStride];
-    const ClipArg& c = a.clip;
+// One tile: 64 frames of clip c starting at frame tile `tile`, scale super-group sg.
+__device__ __forceinline__ void direct_tile(const DirectArgs& a, const ClipArg& c, int tile, int sg,
+                                            float* X) {
     const int gpw = kDirectWaves;                                   // groups per work-group
-    const int nsg = (a.ngroups + gpw - 1) / gpw;
-    int id = blockIdx.x;
-    if (a.xcd_remap) id = xcd_remap_d(id, gridDim.x);
-    const int tile = id / nsg, sg = id - tile * nsg;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t k0 = (int64_t)tile * kDirectFrames;
@@ -80,6 +76,34 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
     }
 }
 
+
+__global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
+    __shared__ float X[kDirectChunk * kRowStride];
+    const int nsg = (a.ngroups + kDirectWaves - 1) / kDirectWaves;
+    int id = blockIdx.x;
+    if (a.xcd_remap) id = xcd_remap_d(id, gridDim.x);
+    const int tile = id / nsg, sg = id - tile * nsg;
+    direct_tile(a, a.clip, tile, sg, X);
+}
+
+// Batch: a flat grid over the tiles of every clip; clip c owns tiles
+// [prefix[c], prefix[c+1]).
+__global__ __launch_bounds__(256) void k_direct_batch(DirectArgs a, const ClipArg* __restrict__ clips,
+                                                      const int32_t* __restrict__ prefix, int nclips) {
+    __shared__ float X[kDirectChunk * kRowStride];
+    const int nsg = (a.ngroups + kDirectWaves - 1) / kDirectWaves;
+    const int t = blockIdx.x;
+    int lo = 0, hi = nclips - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int local = t - prefix[lo];
+    const int tile = local / nsg, sg = local - tile * nsg;
+    const ClipArg c = clips[lo];
+    direct_tile(a, c, tile, sg, X);
+}
+
 hipError_t launch_direct(const DirectArgs& a, hipStream_t s) {
     const int nsg = (a.ngroups + kDirectWaves - 1) / kDirectWaves;
     const int64_t ntile = a.clip.ntile;
@@ -87,6 +111,15 @@ hipError_t launch_direct(const DirectArgs& a, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_direct, dim3((unsigned)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, const int32_t* d_prefix,
+                               int nclips, int total_tiles, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_direct_batch, dim3((unsigned)total_tiles), dim3(256), 0, s, a, d_clips,
+                       d_prefix, nclips);
     return hipGetLastError();
 }
 

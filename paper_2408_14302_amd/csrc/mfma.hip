@@ -197,20 +197,23 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// Power-of-two signal scale beta = 2^floor(log2(448 / max|x~|)) over the tile window.
+// Power-of-two signal scale beta = 2^floor(log2(448 / max|x~|)), the maximum
+// taken over exactly the samples the tile's frames touch (the union of the
+// windows [(k0+f)*hop + KS*glo, (k0+f)*hop + KS*(ghi+1)) ), so beta depends only
+// on the tile's frame range and the scale group, never on the staging layout.
 template <int DT>
 __device__ float tile_beta(const ClipArg& c, int F, int64_t k0, int glo, int ghi, float* red) {
     using T = Tr<DT>;
     float m = 0.0f;
     const int nt = kMfmaWaves * kWaveSize;
-    if (c.mode == STAGE_LINEAR) {
+    const int64_t w = (int64_t)T::KS * (ghi - glo + 1);   // one frame's window
+    if (c.hop <= w) {                                     // windows overlap: one range
         int64_t a = k0 * c.hop + (int64_t)T::KS * glo;
         int64_t b = (k0 + F - 1) * c.hop + (int64_t)T::KS * (ghi + 1);
         if (a < 0) a = 0;
         if (b > c.len) b = c.len;
         for (int64_t j = a + threadIdx.x; j < b; j += nt) m = fmaxf(m, fabsf(c.x[j]));
     } else {
-        int64_t w = (int64_t)T::KS * (ghi - glo + 1);
         for (int f = 0; f < F; ++f) {
             int64_t a = (k0 + f) * c.hop + (int64_t)T::KS * glo, b = a + w;
             if (a < 0) a = 0;
@@ -219,9 +222,9 @@ __device__ float tile_beta(const ClipArg& c, int F, int64_t k0, int glo, int ghi
         }
     }
     m = wave_max(m);
-    int w = threadIdx.x / kWaveSize;
+    int wv = threadIdx.x / kWaveSize;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = m;
+    if ((threadIdx.x & 63) == 0) red[wv] = m;
     __syncthreads();
     m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
     if (m == 0.0f) return 1.0f;

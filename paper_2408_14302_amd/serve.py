@@ -1,0 +1,253 @@
+"""Continuous-batching scalogram server.
+
+Requests (a resident clip, a scale set, a hop) arrive over time.  The scheduler
+admits them in arrival order as long as the HBM footprint of the outputs in
+flight (n_scales * K * 4 bytes each) stays within a budget and a stream slot is
+free; the admitted requests of one scale set go to the GPU as ONE persistent
+launch (cwt_batch_execute) on that slot's stream, so batches on different slots
+overlap on the device.  Completed batches free their footprint and slot, and
+the loop admits more.  A request larger than the whole budget is rejected.
+Plans (and the wavelet banks behind them) stay resident for the whole session.
+
+The scheduling logic (class Scheduler) holds no GPU state; the executor
+interface is two calls, ``launch(requests) -> handle`` and ``done(handle)``,
+so the logic is testable with a scripted executor on the CPU.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float           # seconds on the session clock
+    n: int                   # samples
+    scale_key: Any           # requests with equal keys can share a launch
+    hop: int
+    footprint: int           # output bytes
+    payload: Any = None      # executor-specific (device tensor, plan, ...)
+    admitted: Optional[float] = None
+    completed: Optional[float] = None
+    rejected: bool = False
+    output: Any = None
+
+
+@dataclass
+class Stats:
+    latencies_ms: List[float] = field(default_factory=list)
+    admitted: int = 0
+    rejected: int = 0
+    batches: int = 0
+    max_inflight_bytes: int = 0
+    coefficients: int = 0
+    wall_s: float = 0.0
+    busy_slots_max: int = 0
+
+    def summary(self) -> Dict[str, float]:
+        lat = np.asarray(self.latencies_ms, dtype=np.float64)
+        out = {
+            "completed": int(lat.size),
+            "admitted": self.admitted,
+            "rejected": self.rejected,
+            "batches": self.batches,
+            "max_inflight_bytes": self.max_inflight_bytes,
+            "max_concurrent_batches": self.busy_slots_max,
+            "wall_s": self.wall_s,
+            "coeffs_per_s": self.coefficients / self.wall_s if self.wall_s > 0 else 0.0,
+        }
+        if lat.size:
+            out.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "mean_ms": float(lat.mean()), "max_ms": float(lat.max())})
+        return out
+
+
+class Scheduler:
+    """Admission by output footprint, FIFO order, up to `slots` batches in flight."""
+
+    def __init__(self, executor, budget_bytes: int, slots: int = 2, max_batch: int = 64,
+                 clock: Callable[[], float] = time.perf_counter):
+        if budget_bytes <= 0 or slots < 1 or max_batch < 1:
+            raise ValueError("budget, slots and max_batch must be positive")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.queue: collections.deque = collections.deque()
+        self.inflight: Dict[int, tuple] = {}   # slot -> (handle, [requests], bytes)
+        self.inflight_bytes = 0
+        self.stats = Stats()
+
+    def offer(self, req: Request) -> None:
+        if req.footprint > self.budget:
+            req.rejected = True
+            self.stats.rejected += 1
+            return
+        self.queue.append(req)
+
+    def _free_slot(self) -> Optional[int]:
+        for s in range(self.slots):
+            if s not in self.inflight:
+                return s
+        return None
+
+    def admit(self, now: float) -> int:
+        """Form and launch batches while budget and slots allow.  Requests are
+        taken in arrival order; a batch holds the head request's scale set and
+        the following requests of the same set that fit."""
+        launched = 0
+        while self.queue:
+            slot = self._free_slot()
+            if slot is None:
+                break
+            head = self.queue[0]
+            if self.inflight_bytes + head.footprint > self.budget:
+                break   # FIFO: nobody overtakes a head that does not fit yet
+            batch, used, keep = [], 0, collections.deque()
+            while self.queue and len(batch) < self.max_batch:
+                r = self.queue.popleft()
+                if (r.scale_key == head.scale_key
+                        and self.inflight_bytes + used + r.footprint <= self.budget):
+                    batch.append(r)
+                    used += r.footprint
+                else:
+                    keep.append(r)
+                    if r.scale_key == head.scale_key:
+                        break   # the next same-set request no longer fits: stop here
+            keep.extend(self.queue)
+            self.queue = keep
+            for r in batch:
+                r.admitted = now
+            handle = self.ex.launch(slot, batch)
+            self.inflight[slot] = (handle, batch, used)
+            self.inflight_bytes += used
+            self.stats.admitted += len(batch)
+            self.stats.batches += 1
+            self.stats.max_inflight_bytes = max(self.stats.max_inflight_bytes, self.inflight_bytes)
+            self.stats.busy_slots_max = max(self.stats.busy_slots_max, len(self.inflight))
+            launched += 1
+        return launched
+
+    def poll(self, now: float) -> int:
+        finished = 0
+        for slot in list(self.inflight):
+            handle, batch, used = self.inflight[slot]
+            if self.ex.done(handle):
+                t = self.clock()
+                for r in batch:
+                    r.completed = t
+                    self.stats.latencies_ms.append((t - r.arrival) * 1e3)
+                    self.stats.coefficients += r.footprint // 4
+                self.ex.release(slot, batch)
+                del self.inflight[slot]
+                self.inflight_bytes -= used
+                finished += 1
+        return finished
+
+    def run(self, requests: Sequence[Request], t0: Optional[float] = None) -> Stats:
+        """Serve `requests` (sorted by arrival, times relative to t0)."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.clock() if t0 is None else t0
+        i = 0
+        while i < len(reqs) or self.queue or self.inflight:
+            now = self.clock() - t0
+            while i < len(reqs) and reqs[i].arrival <= now:
+                r = reqs[i]
+                r.arrival += t0   # to absolute clock for latency
+                self.offer(r)
+                i += 1
+            self.poll(now)
+            self.admit(now)
+            if not self.queue and not self.inflight and i < len(reqs):
+                # idle until the next arrival
+                wait = reqs[i].arrival - (self.clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.0005))
+        self.stats.wall_s = self.clock() - t0
+        return self.stats
+
+
+# ---------------------------------------------------------------------------
+# GPU executor: one batch context and one stream per slot.
+
+class GpuExecutor:
+    """Runs each admitted batch as one persistent launch on the slot's stream."""
+
+    def __init__(self, slots: int, max_clips: int = 256, keep_outputs: bool = False):
+        import torch
+
+        from . import cwth
+        self.torch = torch
+        self.cwth = cwth
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]   # default priority
+        self.batches = [cwth.Batch(max_clips) for _ in range(slots)]
+        self.keep = keep_outputs
+
+    def launch(self, slot: int, batch: List[Request]):
+        torch = self.torch
+        st = self.streams[slot]
+        plans = [r.payload[1] for r in batch]
+        xs = [r.payload[0] for r in batch]
+        with torch.cuda.stream(st):
+            outs = [torch.empty((p.num_scales, p.num_frames(x.numel())), dtype=torch.float32, device=x.device)
+                    for p, x in zip(plans, xs)]
+            # inputs were produced on another stream: order them before this launch
+            self.batches[slot](plans, xs, outs, stream=st, graph=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        for r, o in zip(batch, outs):
+            r.output = o
+        return ev
+
+    def done(self, handle) -> bool:
+        return handle.query()
+
+    def release(self, slot: int, batch: List[Request]) -> None:
+        if not self.keep:
+            for r in batch:
+                r.output = None
+
+
+def poisson_requests(seed: int, count: int, qps: float, clips: Sequence[Any], plans: Dict,
+                     scale_sets: Sequence[int], hops: Sequence[int]) -> List[Request]:
+    """Arrival times with exponential gaps (rate qps); each request picks a clip
+    (resident), a scale count and a hop at random."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    t = 0.0
+    out = []
+    for i in range(int(count)):
+        t += rng.exponential(1.0 / qps)
+        x = clips[int(rng.integers(0, len(clips)))]
+        S = int(scale_sets[int(rng.integers(0, len(scale_sets)))])
+        h = int(hops[int(rng.integers(0, len(hops)))])
+        p = plans[(S, h)]
+        n = int(x.numel())
+        K = -(-n // h)
+        out.append(Request(rid=i, arrival=t, n=n, scale_key=S, hop=h, footprint=S * K * 4, payload=(x, p)))
+    return out
+
+
+def serve_session(qps: float, duration_s: float, clips, plans, scale_sets=(64, 128), hops=(1, 256, 512),
+                  budget_bytes: int = 4 << 30, slots: int = 3, max_batch: int = 64, seed: int = 1430400,
+                  keep_outputs: bool = False, executor: Optional[GpuExecutor] = None):
+    """One Poisson session on the GPU; returns (Stats, requests).  Pass the same
+    executor to several sessions to keep its batch contexts (and their captured
+    graphs) warm."""
+    import torch
+    count = max(1, int(round(qps * duration_s)))
+    reqs = poisson_requests(seed, count, qps, clips, plans, scale_sets, hops)
+    ex = executor or GpuExecutor(slots, max_clips=max_batch, keep_outputs=keep_outputs)
+    if len(ex.streams) < slots:
+        raise ValueError("executor has fewer streams than slots")
+    sch = Scheduler(ex, budget_bytes, slots=slots, max_batch=max_batch)
+    torch.cuda.synchronize()
+    stats = sch.run(reqs)
+    torch.cuda.synchronize()
+    return stats, reqs

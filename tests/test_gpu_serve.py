@@ -1,0 +1,42 @@
+"""Serving on the GPU: requests admitted while others run, overlapping
+batches on several streams, and every result bit-identical to the same request
+run alone (the summation order does not depend on the batch)."""
+import numpy as np
+import pytest
+
+from gpu_util import torch_cuda
+from paper_2408_14302_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_results_same_alone_and_in_the_mix():
+    torch = torch_cuda()
+    from paper_2408_14302_amd import cwth, serve
+    lens = np.clip(synth.serving_lengths(11, 16) // 4, 4000, 60000)
+    clips = [torch.from_numpy(synth.make_clip(900 + i, int(n), 16000.0, 0.0)).cuda() for i, n in enumerate(lens)]
+    plans = {(s, h): cwth.Plan(16000.0, synth.linear_scales(s), h, "bf16") for s in (64, 128) for h in (1, 256, 512)}
+    stats, reqs = serve.serve_session(4000.0, 0.05, clips, plans, seed=3, keep_outputs=True, max_batch=16)
+    sm = stats.summary()
+    print(sm)
+    assert sm["completed"] == len(reqs) and sm["rejected"] == 0
+    assert sm["batches"] >= 2
+    for r in reqs:
+        x, p = r.payload
+        alone = p(x)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, r.output), r.rid
+
+
+def test_budget_and_rejection_on_gpu():
+    torch = torch_cuda()
+    from paper_2408_14302_amd import cwth, serve
+    clips = [torch.from_numpy(synth.make_clip(950 + i, 20000, 16000.0, 0.0)).cuda() for i in range(4)]
+    plans = {(s, h): cwth.Plan(16000.0, synth.linear_scales(s), h, "bf16") for s in (64, 128) for h in (1, 256, 512)}
+    # a budget below one hop-1 request (64 x 20000 x 4 B) rejects those, serves the rest
+    stats, reqs = serve.serve_session(2000.0, 0.05, clips, plans, seed=4, budget_bytes=4 << 20,
+                                      keep_outputs=False)
+    sm = stats.summary()
+    assert sm["max_inflight_bytes"] <= 4 << 20
+    assert sm["rejected"] == sum(1 for r in reqs if r.footprint > (4 << 20)) > 0
+    assert sm["completed"] == len(reqs) - sm["rejected"]
