@@ -15,7 +15,6 @@ enum Dtype : int { DT_FP32 = 0, DT_BF16 = 1, DT_FP16 = 2, DT_BF16X3 = 3, DT_FP8 
 constexpr int kBlockRows = 32;     // scales per MFMA block (the M side of 32x32xK)
 constexpr int kWaveSize = 64;
 constexpr int kMfmaWaves = 4;      // waves per MFMA work-group (split along frames)
-constexpr int kMaxGroupBlocks = 4; // blocks one MFMA work-group contracts at once
 constexpr int kDirectFrames = 64;  // frames per direct-sum work-group (one per lane)
 constexpr int kDirectRows = 4;     // scales per direct-sum wave
 constexpr int kDirectWaves = 4;    // waves per direct-sum work-group
@@ -52,15 +51,6 @@ struct MfmaBlock {
     float inv_alpha[kBlockRows]; // FP8 only: 1/alpha_r; 1 otherwise
 };
 
-// A group is what one work-group contracts: up to kMaxGroupBlocks blocks with
-// nested K ranges, listed by ascending range (so the blocks active at step ks
-// are a suffix of the list).
-struct MfmaGroup {
-    int32_t nblk;
-    int32_t blk[kMaxGroupBlocks]; // indices into the block table
-    int32_t lo, hi;               // union of the member ranges (= widest block)
-};
-
 // ---------------------------------------------------------------------------
 // Per-launch arguments.
 
@@ -83,8 +73,7 @@ enum StageMode : int { STAGE_LINEAR = 0, STAGE_ROWS = 1 };
 struct MfmaArgs {
     const uint8_t* frags;
     const MfmaBlock* blocks;
-    const MfmaGroup* groups;
-    int32_t ngroups;
+    int32_t ngroups;       // number of 32-scale blocks (one per work-group tile)
     int32_t signed_out;
     int32_t chunk_steps;   // K-steps staged per LDS chunk
     int32_t frames;        // frames per tile (= 32 * A * kMfmaWaves)
@@ -113,7 +102,7 @@ struct DirectArgs {
 hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
 hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, const int32_t* d_prefix,
                                int nclips, int total_tiles, hipStream_t s);
-// cfgA = frame blocks per wave (1, 2, 4); nb = blocks per group bound (1, 2, 4).
+// A = 32-frame blocks per wave (1, 2, 4); the third argument is unused.
 hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,
                        int grid, hipStream_t s);
 int mfma_max_lds_bytes();

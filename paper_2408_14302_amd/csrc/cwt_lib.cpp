@@ -162,11 +162,8 @@ struct Bank {
     DirectGroup* d_dgroups = nullptr;
     // mfma
     std::vector<MfmaBlock> blocks;
-    std::vector<MfmaGroup> groups;
-    int nb_max = 1;
     uint8_t* d_frags = nullptr;
     MfmaBlock* d_blocks = nullptr;
-    MfmaGroup* d_groups = nullptr;
     int64_t frag_bytes = 0;
     int Mmax = 0;
 
@@ -175,7 +172,6 @@ struct Bank {
         if (d_dgroups) (void)hipFree(d_dgroups);
         if (d_frags) (void)hipFree(d_frags);
         if (d_blocks) (void)hipFree(d_blocks);
-        if (d_groups) (void)hipFree(d_groups);
     }
 };
 
@@ -263,42 +259,12 @@ static cwt_status build_bank(int dt, int device, const std::vector<double>& scal
             bk->blocks.push_back(B);
         }
         bk->frag_bytes = off;
-        // Groups of at most four blocks.  More than four blocks: deal blocks
-        // (widest first) to groups in snake order to balance the K-steps.
-        const int ngr = (nbk + kMaxGroupBlocks - 1) / kMaxGroupBlocks;
-        std::vector<std::vector<int>> members(ngr);
-        std::vector<int> byw(nbk);
-        std::iota(byw.begin(), byw.end(), 0);
-        std::sort(byw.begin(), byw.end(), [&](int a, int b) {
-            return bk->blocks[a].hi - bk->blocks[a].lo > bk->blocks[b].hi - bk->blocks[b].lo;
-        });
-        for (int i = 0; i < nbk; ++i) {
-            int round = i / ngr, pos = i % ngr;
-            int g = (round % 2 == 0) ? pos : ngr - 1 - pos;
-            members[g].push_back(byw[i]);
-        }
-        bk->nb_max = 1;
-        for (int g = 0; g < ngr; ++g) {
-            auto& m = members[g];
-            std::sort(m.begin(), m.end(), [&](int a, int b) {
-                return bk->blocks[a].hi - bk->blocks[a].lo < bk->blocks[b].hi - bk->blocks[b].lo;
-            });
-            MfmaGroup G;
-            G.nblk = (int)m.size();
-            for (int i = 0; i < kMaxGroupBlocks; ++i) G.blk[i] = i < G.nblk ? m[i] : 0;
-            G.lo = bk->blocks[m.back()].lo;
-            G.hi = bk->blocks[m.back()].hi;
-            bk->groups.push_back(G);
-            bk->nb_max = std::max(bk->nb_max, G.nblk);
-        }
         HIP_TRY(hipMalloc(&d_alpha, sizeof(double) * S), "alpha");
         std::unique_ptr<double, void (*)(double*)> g2(d_alpha, [](double* p) { (void)hipFree(p); });
         HIP_TRY(hipMemcpy(d_alpha, alpha.data(), sizeof(double) * S, hipMemcpyHostToDevice), "alpha copy");
         HIP_TRY(hipMalloc(&bk->d_frags, off), "mfma bank");
         HIP_TRY(hipMalloc(&bk->d_blocks, sizeof(MfmaBlock) * nbk), "mfma blocks");
-        HIP_TRY(hipMalloc(&bk->d_groups, sizeof(MfmaGroup) * ngr), "mfma groups");
         HIP_TRY(hipMemcpy(bk->d_blocks, bk->blocks.data(), sizeof(MfmaBlock) * nbk, hipMemcpyHostToDevice), "blocks copy");
-        HIP_TRY(hipMemcpy(bk->d_groups, bk->groups.data(), sizeof(MfmaGroup) * ngr, hipMemcpyHostToDevice), "groups copy");
         HIP_TRY(gen_mfma_bank(dt, d_sorted, S, bk->d_blocks, nbk, bk->d_frags, off, d_alpha, 0), "mfma bank generation");
         HIP_TRY(hipDeviceSynchronize(), "bank generation");
     }
@@ -396,7 +362,6 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     if (p->dt == DT_FP32) return cfg == 0;
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
     const MfmaCfg& c = kMfmaCfgs[cfg];
-    if (c.A == 4 && p->bank->nb_max > 2) return false;   // register budget
     // FP8 scales the signal per 128-frame tile; a fixed tile keeps every clip's
     // result independent of the configuration and of the batch it runs in.
     if (p->dt == DT_FP8 && c.A != 1) return false;
@@ -447,8 +412,7 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
     std::memset(&a, 0, sizeof(a));
     a.frags = bk.d_frags;
     a.blocks = bk.d_blocks;
-    a.groups = bk.d_groups;
-    a.ngroups = (int)bk.groups.size();
+    a.ngroups = (int)bk.blocks.size();
     a.signed_out = p->signed_out;
     a.chunk_steps = c.chunk;
     a.frames = F;
@@ -458,7 +422,7 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
     a.xcd_remap = 1;
     int64_t grid = (int64_t)a.clip.ntile * a.ngroups;
     if (grid > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
-    HIP_TRY(launch_mfma(p->dt, c.A, bk.nb_max, a, 0, (int)grid, stream), "mfma launch");
+    HIP_TRY(launch_mfma(p->dt, c.A, 1, a, 0, (int)grid, stream), "mfma launch");
     return CWT_OK;
 }
 
@@ -572,7 +536,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     const MfmaCfg c = fp32 ? MfmaCfg{1, 1} : kMfmaCfgs[cfg];
     const int F = fp32 ? kDirectFrames : 128 * c.A;
     const int64_t groups_per_tile = fp32 ? ((int64_t)bk.dgroups.size() + kDirectWaves - 1) / kDirectWaves
-                                         : (int64_t)bk.groups.size();
+                                         : (int64_t)bk.blocks.size();
 
     // Wait until the pinned buffer we are about to overwrite has been consumed.
     const int slot = b->flip;
@@ -627,8 +591,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     std::memset(&a, 0, sizeof(a));
     a.frags = bk.d_frags;
     a.blocks = bk.d_blocks;
-    a.groups = bk.d_groups;
-    a.ngroups = (int)bk.groups.size();
+    a.ngroups = (int)bk.blocks.size();
     a.signed_out = p0->signed_out;
     a.chunk_steps = c.chunk;
     a.frames = F;
@@ -640,21 +603,21 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.nclips = nc;
     a.total_tiles = (int32_t)total;
     a.counter = b->d_counter;
-    const int grid = persistent_grid(b->cus, p0->dt, c.A, bk.nb_max, 2 * maxbytes);
+    const int grid = persistent_grid(b->cus, p0->dt, c.A, 1, 2 * maxbytes);
 
     if (!use_graph) {
         HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
-        HIP_TRY(launch_mfma(p0->dt, c.A, bk.nb_max, a, 1, grid, stream), "persistent launch");
+        HIP_TRY(launch_mfma(p0->dt, c.A, 1, a, 1, grid, stream), "persistent launch");
     } else {
         // Kernel arguments that vary per batch (nclips, total tiles, prefix
         // address) are part of the captured node, so graphs are cached per
         // (shape) and their kernel node parameters refreshed before replay.
-        auto key = std::make_tuple(p0->dt, c.A, bk.nb_max, (int)maxbytes, grid, c.chunk);
+        auto key = std::make_tuple(p0->dt, c.A, 1, (int)maxbytes, grid, c.chunk);
         GraphEntry& ge = b->graphs[key];
         if (!ge.exec) {
             HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
             hipError_t e1 = hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream);
-            hipError_t e2 = launch_mfma(p0->dt, c.A, bk.nb_max, a, 1, grid, b->cap_stream);
+            hipError_t e2 = launch_mfma(p0->dt, c.A, 1, a, 1, grid, b->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e3 = hipStreamEndCapture(b->cap_stream, &g);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {

@@ -144,50 +144,171 @@ __device__ __forceinline__ int swizzle(int unit, int swz) {
     return swz >= 0 ? (unit ^ ((unit >> swz) & 15)) : unit;
 }
 
-// Stage chunk (first K-step ks_c) into LDS buffer `buf`.
+// ---------------------------------------------------------------------------
+// Staging.  One chunk of signal is brought in with aligned float4 loads into
+// registers before the MFMAs of the previous chunk are issued, and converted
+// and written to LDS after them, so the global-load latency overlaps the
+// matrix work.  A LINEAR unit is a span of 2U floats that supplies one 16-byte
+// unit to every shifted copy; a ROWS unit is U floats of one frame's row.
+// Per-thread register budget of one prefetched chunk: one LINEAR span (2U floats).
 template <int DT>
-__device__ __forceinline__ void stage_chunk(const ClipArg& c, const Geo& g, int F, int chunk,
-                                            int64_t k0, int ks_c, float beta, bool aligned16,
-                                            uint8_t* buf) {
-    using T = Tr<DT>;
-    const float* __restrict__ x = c.x;
-    const int64_t len = c.len;
-    const int tid = threadIdx.x;
-    int total;
-    int per_row = T::KS * chunk / T::U;   // rows mode: units per row
-    if (g.mode == STAGE_LINEAR) total = g.copies * g.len_u;
-    else total = F * per_row;
-    for (int q = tid; q < total; q += kMfmaWaves * kWaveSize) {
-        int64_t j;
-        int dst_unit;
-        if (g.mode == STAGE_LINEAR) {
-            int cp = q / g.len_u, uu = q - cp * g.len_u;
-            j = k0 * c.hop + (int64_t)T::KS * ks_c + cp * g.gh + uu * T::U;
-            dst_unit = cp * g.cs + swizzle(uu, g.swz);
-        } else {
+__device__ constexpr int stage_floats() { return 2 * Tr<DT>::U; }
+
+template <int DT>
+__device__ constexpr int upt_linear() { return stage_floats<DT>() / (2 * Tr<DT>::U); }
+template <int DT>
+__device__ constexpr int upt_rows() { return stage_floats<DT>() / Tr<DT>::U; }
+
+template <int CNT, int OFF, int N>
+__device__ __forceinline__ void load_span(const float* __restrict__ x, int64_t len, int64_t j,
+                                          bool al16, float (&v)[N]) {
+    static_assert(OFF + CNT <= N, "span outside the register array");
+    if (j >= 0 && j + CNT <= len && al16 && (j & 3) == 0) {
+#pragma unroll
+        for (int e = 0; e < CNT; e += 4) {
+            float4 f4 = *(const float4*)(x + j + e);
+            v[OFF + e] = f4.x; v[OFF + e + 1] = f4.y; v[OFF + e + 2] = f4.z; v[OFF + e + 3] = f4.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < CNT; ++e) {
+            int64_t jj = j + e;
+            v[OFF + e] = (jj >= 0 && jj < len) ? x[jj] : 0.0f;
+        }
+    }
+}
+
+// pack_unit of v[OFF+sh .. OFF+sh+U-1] for a run-time shift sh in [0, U) (uniform).
+template <int DT, int OFF, int N, int S = 0>
+__device__ __forceinline__ void pack_shift(const float (&v)[N], int sh, float beta, i32x4* pk) {
+    if constexpr (S < Tr<DT>::U) {
+        if (sh == S) {
+            float t[Tr<DT>::U];
+#pragma unroll
+            for (int e = 0; e < Tr<DT>::U; ++e) t[e] = v[OFF + S + e];
+            pack_unit<DT>(t, beta, pk);
+            return;
+        }
+        pack_shift<DT, OFF, N, S + 1>(v, sh, beta, pk);
+    }
+}
+
+template <int DT, int OFF, int N>
+__device__ __forceinline__ void pack_at(const float (&v)[N], float beta, i32x4* pk) {
+    float t[Tr<DT>::U];
+#pragma unroll
+    for (int e = 0; e < Tr<DT>::U; ++e) t[e] = v[OFF + e];
+    pack_unit<DT>(t, beta, pk);
+}
+
+template <int DT>
+__device__ __forceinline__ void put_unit(uint8_t* lds, int off, int plane_bytes, const i32x4* pk) {
+#pragma unroll
+    for (int p = 0; p < Tr<DT>::PLANES; ++p) *(i32x4*)(lds + off + p * plane_bytes) = pk[p];
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void stage_load_lin(const ClipArg& c, const Geo& g, int64_t jb, bool al16,
+                                               float (&r)[2 * Tr<DT>::U]) {
+    constexpr int UP = upt_linear<DT>(), SP = 2 * Tr<DT>::U;
+    if constexpr (I < UP) {
+        const int uu = threadIdx.x + I * 256;
+        if (uu < g.len_u) load_span<SP, I * SP>(c.x, c.len, jb + (int64_t)uu * Tr<DT>::U, al16, r);
+        stage_load_lin<DT, I + 1>(c, g, jb, al16, r);
+    }
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void stage_load_rows(const ClipArg& c, int F, int per_row, int64_t k0, int ks_c,
+                                                bool al16, float (&r)[2 * Tr<DT>::U]) {
+    constexpr int UP = upt_rows<DT>(), SP = Tr<DT>::U;
+    if constexpr (I < UP) {
+        const int q = threadIdx.x + I * 256;
+        if (q < F * per_row) {
             int f = q / per_row, cu = q - f * per_row;
-            j = (k0 + f) * c.hop + (int64_t)T::KS * ks_c + cu * T::U;
-            dst_unit = f * g.rs + cu;
+            int64_t j = (k0 + f) * c.hop + (int64_t)Tr<DT>::KS * ks_c + cu * Tr<DT>::U;
+            load_span<SP, I * SP>(c.x, c.len, j, al16, r);
         }
-        float v[T::U];
-        if (j >= 0 && j + T::U <= len && aligned16 && (j & 3) == 0) {
-#pragma unroll
-            for (int e = 0; e < T::U; e += 4) {
-                float4 f4 = *(const float4*)(x + j + e);
-                v[e] = f4.x; v[e + 1] = f4.y; v[e + 2] = f4.z; v[e + 3] = f4.w;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < T::U; ++e) {
-                int64_t jj = j + e;
-                v[e] = (jj >= 0 && jj < len) ? x[jj] : 0.0f;
+        stage_load_rows<DT, I + 1>(c, F, per_row, k0, ks_c, al16, r);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void stage_load(const ClipArg& c, const Geo& g, int F, int chunk, int64_t k0,
+                                           int ks_c, bool al16, float (&r)[2 * Tr<DT>::U]) {
+    using T = Tr<DT>;
+    if (g.mode == STAGE_LINEAR)
+        stage_load_lin<DT>(c, g, k0 * c.hop + (int64_t)T::KS * ks_c, al16, r);
+    else
+        stage_load_rows<DT>(c, F, T::KS * chunk / T::U, k0, ks_c, al16, r);
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void stage_store_lin(const Geo& g, float beta, const float (&r)[2 * Tr<DT>::U],
+                                                uint8_t* lds, int buf) {
+    constexpr int UP = upt_linear<DT>(), SP = 2 * Tr<DT>::U;
+    if constexpr (I < UP) {
+        const int uu = threadIdx.x + I * 256;
+        if (uu < g.len_u) {
+            const int su = swizzle(uu, g.swz);
+            i32x4 pk[Tr<DT>::PLANES];
+            for (int cp = 0; cp < g.copies; ++cp) {
+                pack_shift<DT, I * SP>(r, cp * g.gh, beta, pk);
+                put_unit<DT>(lds, buf + (cp * g.cs + su) * 16, g.plane_bytes, pk);
             }
         }
-        i32x4 pk[T::PLANES];
-        pack_unit<DT>(v, beta, pk);
-#pragma unroll
-        for (int p = 0; p < T::PLANES; ++p)
-            *(i32x4*)(buf + p * g.plane_bytes + dst_unit * 16) = pk[p];
+        stage_store_lin<DT, I + 1>(g, beta, r, lds, buf);
+    }
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void stage_store_rows(const Geo& g, int F, int per_row, float beta,
+                                                 const float (&r)[2 * Tr<DT>::U], uint8_t* lds, int buf) {
+    constexpr int UP = upt_rows<DT>(), SP = Tr<DT>::U;
+    if constexpr (I < UP) {
+        const int q = threadIdx.x + I * 256;
+        if (q < F * per_row) {
+            int f = q / per_row, cu = q - f * per_row;
+            i32x4 pk[Tr<DT>::PLANES];
+            pack_at<DT, I * SP>(r, beta, pk);
+            put_unit<DT>(lds, buf + (f * g.rs + cu) * 16, g.plane_bytes, pk);
+        }
+        stage_store_rows<DT, I + 1>(g, F, per_row, beta, r, lds, buf);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void stage_store(const ClipArg& c, const Geo& g, int F, int chunk, int64_t k0,
+                                            int ks_c, bool al16, float beta, const float (&r)[2 * Tr<DT>::U],
+                                            uint8_t* lds, int buf) {
+    using T = Tr<DT>;
+    i32x4 pk[T::PLANES];
+    if (g.mode == STAGE_LINEAR) {
+        constexpr int UP = upt_linear<DT>(), SP = 2 * T::U;
+        stage_store_lin<DT>(g, beta, r, lds, buf);
+        // units beyond the register budget: load and store directly
+        const int64_t jb = k0 * c.hop + (int64_t)T::KS * ks_c;
+        for (int uu = threadIdx.x + UP * 256; uu < g.len_u; uu += 256) {
+            float v[SP];
+            load_span<SP, 0>(c.x, c.len, jb + (int64_t)uu * T::U, al16, v);
+            const int su = swizzle(uu, g.swz);
+            for (int cp = 0; cp < g.copies; ++cp) {
+                pack_shift<DT, 0>(v, cp * g.gh, beta, pk);
+                put_unit<DT>(lds, buf + (cp * g.cs + su) * 16, g.plane_bytes, pk);
+            }
+        }
+    } else {
+        constexpr int UP = upt_rows<DT>(), SP = T::U;
+        const int per_row = T::KS * chunk / T::U, total = F * per_row;
+        stage_store_rows<DT>(g, F, per_row, beta, r, lds, buf);
+        for (int q = threadIdx.x + UP * 256; q < total; q += 256) {
+            int f = q / per_row, cu = q - f * per_row;
+            int64_t j = (k0 + f) * c.hop + (int64_t)T::KS * ks_c + cu * T::U;
+            float v[SP];
+            load_span<SP, 0>(c.x, c.len, j, al16, v);
+            pack_at<DT, 0>(v, beta, pk);
+            put_unit<DT>(lds, buf + (f * g.rs + cu) * 16, g.plane_bytes, pk);
+        }
     }
 }
 
@@ -233,123 +354,157 @@ __device__ float tile_beta(const ClipArg& c, int F, int64_t k0, int glo, int ghi
     return (float)ldexp(1.0, e - 1);
 }
 
-template <int DT, int A, int NB>
-__device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
-                                             uint8_t* lds, float* red) {
+template <int DT>
+__device__ __forceinline__ void load_tap(const uint8_t* __restrict__ tp, int lane, Frag<DT>& t) {
     using T = Tr<DT>;
-    const int F = 32 * A * kMfmaWaves;
+    const uint8_t* p0 = tp + lane * T::FRAG;
+#pragma unroll
+    for (int p = 0; p < T::PLANES; ++p)
+#pragma unroll
+        for (int u = 0; u < T::LU; ++u) t.u[p][u] = *((const i32x4*)(p0 + p * 64 * T::FRAG) + u);
+}
+
+// Signal fragments of step d (relative to the chunk's first step) for the
+// lane's A frame blocks.  LINEAR: copy base + swizzled unit; ROWS: row base + unit.
+template <int DT, int A, int MODE>
+__device__ __forceinline__ void load_x(const uint8_t* lds, int buf, int plane_bytes, int swz,
+                                       const int (&base)[A], const int (&unit0)[A], int d, Frag<DT> (&x)[A]) {
+    using T = Tr<DT>;
+#pragma unroll
+    for (int fa = 0; fa < A; ++fa) {
+#pragma unroll
+        for (int u = 0; u < T::LU; ++u) {
+            int off;
+            if constexpr (MODE == STAGE_LINEAR) {
+                const int unit = unit0[fa] + d * (T::KS / T::U) + u;
+                off = base[fa] + ((unit ^ ((unit >> swz) & 15)) << 4);
+            } else {
+                off = base[fa] + ((d * (T::KS / T::U) + u) << 4);
+            }
+#pragma unroll
+            for (int p = 0; p < T::PLANES; ++p)
+                x[fa].u[p][u] = *(const i32x4*)(lds + buf + p * plane_bytes + off);
+        }
+    }
+}
+
+template <int DT, int A>
+__device__ __forceinline__ void mma_frags(const Frag<DT>& t, const Frag<DT> (&x)[A], f32x16 (&acc)[A]) {
+#pragma unroll
+    for (int fa = 0; fa < A; ++fa) acc[fa] = mma_all<DT>(t, x[fa], acc[fa]);
+}
+
+// K-loop of one tile for a fixed staging layout.  Per chunk: prefetch the next
+// chunk's samples into registers, run the chunk's steps two at a time with
+// ping-pong fragments (the next step's tap and signal fragments are in flight
+// while the current step's MFMAs issue), then write the prefetched samples to
+// the other LDS buffer and synchronise once.
+template <int DT, int A, int MODE>
+__device__ __forceinline__ void tile_loop(const MfmaArgs& a, const ClipArg& c, const Geo& g, int F, int64_t k0,
+                                          int lo, int hi, const uint8_t* __restrict__ tbase, bool al16,
+                                          float beta, uint8_t* lds, f32x16 (&acc)[A]) {
+    using T = Tr<DT>;
     const int chunk = a.chunk_steps;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int n = lane & 31, hg = lane >> 5;
+    const int swz = g.swz < 0 ? 31 : g.swz;        // 31: unit >> 31 == 0, no swizzle
+
+    int base[A], unit0[A];
+#pragma unroll
+    for (int fa = 0; fa < A; ++fa) {
+        const int f = 32 * (A * w + fa) + n;
+        if constexpr (MODE == STAGE_LINEAR) {
+            const int p = f * c.hop + hg * T::PER;
+            base[fa] = ((p % T::U) / g.gh) * g.cs * 16;
+            unit0[fa] = p / T::U;
+        } else {
+            base[fa] = (f * g.rs + hg * T::LU) * 16;
+            unit0[fa] = 0;
+        }
+    }
+    auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
+
+    const int nchunks = (hi - lo + chunk) / chunk;
+    float r[stage_floats<DT>()];
+    stage_load<DT>(c, g, F, chunk, k0, lo, al16, r);
+    stage_store<DT>(c, g, F, chunk, k0, lo, al16, beta, r, lds, 0);
+    Frag<DT> tA, tB, xA[A], xB[A];
+    load_tap<DT>(tap(lo), lane, tA);
+    __syncthreads();
+
+    for (int ci = 0; ci < nchunks; ++ci) {
+        const int ks_c = lo + ci * chunk;
+        const int ns = min(chunk, hi - ks_c + 1);
+        const int buf = (ci & 1) * a.buf_bytes;
+        const bool more = ci + 1 < nchunks;
+        if (more) stage_load<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, r);
+        load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, 0, xA);
+        int d = 0;
+        for (; d + 1 < ns; d += 2) {
+            load_tap<DT>(tap(ks_c + d + 1), lane, tB);
+            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, d + 1, xB);
+            mma_frags<DT, A>(tA, xA, acc);
+            load_tap<DT>(tap(ks_c + d + 2), lane, tA);
+            if (d + 2 < ns) load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, d + 2, xA);
+            mma_frags<DT, A>(tB, xB, acc);
+        }
+        if (d < ns) {                      // odd step count: the last step
+            load_tap<DT>(tap(ks_c + d + 1), lane, tB);
+            mma_frags<DT, A>(tA, xA, acc);
+            tA = tB;
+        }
+        if (more) stage_store<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, beta, r, lds, ((ci + 1) & 1) * a.buf_bytes);
+        __syncthreads();
+    }
+}
+
+// One work-group tile: F = 128*A consecutive frames of one clip against one
+// 32-scale block.  Each wave owns A 32-frame blocks; every K-step is A MFMAs
+// sharing one tap fragment.
+template <int DT, int A>
+__device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c, int tile, int blk,
+                                             uint8_t* lds, float* red) {
+    const int F = 32 * A * kMfmaWaves;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int n = lane & 31, hg = lane >> 5;
     const int64_t k0 = (int64_t)tile * F;
 
-    const MfmaGroup G = a.groups[grp];
-    int lo[NB], hi[NB];
-    int64_t foff[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        if (b < G.nblk) {
-            const MfmaBlock& B = a.blocks[G.blk[b]];
-            lo[b] = B.lo; hi[b] = B.hi; foff[b] = B.frag_off;
-        } else {
-            lo[b] = 1; hi[b] = 0; foff[b] = 0;   // empty range: never active
-        }
-    }
-    const Geo g = make_geo<DT>(c, F, chunk);
-    const bool aligned16 = (((uintptr_t)c.x) & 15) == 0;
+    const MfmaBlock* __restrict__ B = a.blocks + blk;
+    const int lo = B->lo, hi = B->hi;
+    const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
+    const Geo g = make_geo<DT>(c, F, a.chunk_steps);
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
     float beta = 1.0f;
-    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, G.lo, G.hi, red);
+    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, lo, hi, red);
 
-    f32x16 acc[A][NB];
+    f32x16 acc[A];
 #pragma unroll
     for (int fa = 0; fa < A; ++fa)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[fa][b][v] = 0.0f;
+        for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
 
-    const int nchunks = (G.hi - G.lo + chunk) / chunk;
-    uint8_t* bufs[2] = {lds, lds + a.buf_bytes};
-    stage_chunk<DT>(c, g, F, chunk, k0, G.lo, beta, aligned16, bufs[0]);
-    __syncthreads();
-    for (int ci = 0; ci < nchunks; ++ci) {
-        const int ks_c = G.lo + ci * chunk;
-        uint8_t* cur = bufs[ci & 1];
-        if (ci + 1 < nchunks)
-            stage_chunk<DT>(c, g, F, chunk, k0, ks_c + chunk, beta, aligned16, bufs[(ci + 1) & 1]);
-        const int ks_end = min(ks_c + chunk - 1, G.hi);
-        // Per-lane LDS byte offset (copy or row) and first 16-byte unit at ks = ks_c.
-        int base[A], unit0[A];
-#pragma unroll
-        for (int fa = 0; fa < A; ++fa) {
-            const int f = 32 * (A * w + fa) + n;
-            if (g.mode == STAGE_LINEAR) {
-                const int p = f * c.hop + hg * T::PER;
-                base[fa] = ((p % T::U) / g.gh) * g.cs * 16;
-                unit0[fa] = p / T::U;
-            } else {
-                base[fa] = (f * g.rs + hg * T::LU) * 16;
-                unit0[fa] = 0;
-            }
-        }
-        for (int ks = ks_c; ks <= ks_end; ++ks) {
-            const int d = ks - ks_c;
-            Frag<DT> xf[A];
-#pragma unroll
-            for (int fa = 0; fa < A; ++fa) {
-#pragma unroll
-                for (int t = 0; t < T::LU; ++t) {
-                    int off;
-                    if (g.mode == STAGE_LINEAR) {
-                        int unit = unit0[fa] + d * (T::KS / T::U) + t;
-                        off = base[fa] + swizzle(unit, g.swz) * 16;
-                    } else {
-                        off = base[fa] + (d * (T::KS / T::U) + t) * 16;
-                    }
-#pragma unroll
-                    for (int p = 0; p < T::PLANES; ++p)
-                        xf[fa].u[p][t] = *(const i32x4*)(cur + p * g.plane_bytes + off);
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (ks >= lo[b] && ks <= hi[b]) {
-                    const uint8_t* tp = a.frags + foff[b] + (int64_t)(ks - lo[b]) * T::STEP + lane * T::FRAG;
-                    Frag<DT> tf;
-#pragma unroll
-                    for (int p = 0; p < T::PLANES; ++p)
-#pragma unroll
-                        for (int t = 0; t < T::LU; ++t)
-                            tf.u[p][t] = *((const i32x4*)(tp + p * 64 * T::FRAG) + t);
-#pragma unroll
-                    for (int fa = 0; fa < A; ++fa) acc[fa][b] = mma_all<DT>(tf, xf[fa], acc[fa][b]);
-                }
-            }
-        }
-        __syncthreads();
-    }
+    if (g.mode == STAGE_LINEAR)
+        tile_loop<DT, A, STAGE_LINEAR>(a, c, g, F, k0, lo, hi, tbase, al16, beta, lds, acc);
+    else
+        tile_loop<DT, A, STAGE_ROWS>(a, c, g, F, k0, lo, hi, tbase, al16, beta, lds, acc);
 
     // Epilogue: optional descale (FP8), |.| unless signed output, coalesced store.
     const float inv_beta = 1.0f / beta;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        if (b >= G.nblk) continue;
-        const MfmaBlock& B = a.blocks[G.blk[b]];
+    for (int fa = 0; fa < A; ++fa) {
+        const int64_t k = k0 + 32 * (A * w + fa) + n;
+        if (k >= c.K) continue;
 #pragma unroll
-        for (int fa = 0; fa < A; ++fa) {
-            const int64_t k = k0 + 32 * (A * w + fa) + n;
-            if (k >= c.K) continue;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                int r = 8 * (v >> 2) + 4 * hg + (v & 3);
-                int row = B.rows[r];
-                if (row < 0) continue;
-                float val = acc[fa][b][v];
-                if constexpr (DT == DT_FP8) val = val * (B.inv_alpha[r] * inv_beta);
-                if (!a.signed_out) val = fabsf(val);
-                __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
-            }
+        for (int v = 0; v < 16; ++v) {
+            const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
+            const int row = B->rows[rr];
+            if (row < 0) continue;
+            float val = acc[fa][v];
+            if constexpr (DT == DT_FP8) val = val * (B->inv_alpha[rr] * inv_beta);
+            if (!a.signed_out) val = fabsf(val);
+            __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
         }
     }
 }
@@ -362,17 +517,17 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-template <int DT, int A, int NB>
+template <int DT, int A>
 __global__ __launch_bounds__(256) void k_mfma_grid(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ float red[kMfmaWaves];
     int id = blockIdx.x;
     if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
-    int tile = id / a.ngroups, grp = id - tile * a.ngroups;
-    process_tile<DT, A, NB>(a, a.clip, tile, grp, lds, red);
+    const int tile = id / a.ngroups, blk = id - tile * a.ngroups;
+    process_tile<DT, A>(a, a.clip, tile, blk, lds, red);
 }
 
-template <int DT, int A, int NB>
+template <int DT, int A>
 __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ float red[kMfmaWaves];
@@ -389,9 +544,9 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
             if (a.tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const int local = t - a.tile_prefix[lo];
-        const int tile = local / a.ngroups, grp = local - tile * a.ngroups;
+        const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
         const ClipArg c = a.clips[lo];
-        process_tile<DT, A, NB>(a, c, tile, grp, lds, red);
+        process_tile<DT, A>(a, c, tile, blk, lds, red);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -404,78 +559,62 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
     }
 }
 
-template <int DT, int A, int NB>
-static hipError_t launch3(const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
+template <int DT, int A>
+static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
     const size_t shm = 2 * (size_t)a.buf_bytes;
     static bool attr_set[2] = {false, false};
     if (shm > 64 * 1024 && !attr_set[persistent]) {
-        const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A, NB>
-                                    : (const void*)k_mfma_grid<DT, A, NB>;
+        const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A>;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            mfma_max_lds_bytes() - 1024);
         if (e != hipSuccess) return e;
         attr_set[persistent] = true;
     }
     if (persistent)
-        hipLaunchKernelGGL((k_mfma_persistent<DT, A, NB>), dim3(grid), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
     else
-        hipLaunchKernelGGL((k_mfma_grid<DT, A, NB>), dim3(grid), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((k_mfma_grid<DT, A>), dim3(grid), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
-template <int DT, int A>
-static hipError_t launch2(int nb, const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
-    if (nb <= 1) return launch3<DT, A, 1>(a, persistent, grid, s);
-    if (nb <= 2) return launch3<DT, A, 2>(a, persistent, grid, s);
-    return launch3<DT, A, 4>(a, persistent, grid, s);
-}
-
 template <int DT>
-static hipError_t launch1(int A, int nb, const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
-    if (A == 1) return launch2<DT, 1>(nb, a, persistent, grid, s);
-    if (A == 2) return launch2<DT, 2>(nb, a, persistent, grid, s);
-    return launch2<DT, 4>(nb, a, persistent, grid, s);
+static hipError_t launch1(int A, const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
+    if (A == 1) return launch2<DT, 1>(a, persistent, grid, s);
+    if (A == 2) return launch2<DT, 2>(a, persistent, grid, s);
+    return launch2<DT, 4>(a, persistent, grid, s);
 }
 
-hipError_t launch_mfma(int dt, int A, int nb, const MfmaArgs& a, int persistent, int grid,
-                       hipStream_t s) {
+hipError_t launch_mfma(int dt, int A, int, const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
     switch (dt) {
-        case DT_BF16: return launch1<DT_BF16>(A, nb, a, persistent, grid, s);
-        case DT_FP16: return launch1<DT_FP16>(A, nb, a, persistent, grid, s);
-        case DT_BF16X3: return launch1<DT_BF16X3>(A, nb, a, persistent, grid, s);
-        case DT_FP8: return launch1<DT_FP8>(A, nb, a, persistent, grid, s);
+        case DT_BF16: return launch1<DT_BF16>(A, a, persistent, grid, s);
+        case DT_FP16: return launch1<DT_FP16>(A, a, persistent, grid, s);
+        case DT_BF16X3: return launch1<DT_BF16X3>(A, a, persistent, grid, s);
+        case DT_FP8: return launch1<DT_FP8>(A, a, persistent, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 int mfma_max_lds_bytes() { return 160 * 1024; }
 
-template <int DT, int A, int NB>
-static int occ3(int persistent, size_t shm) {
+template <int DT, int A>
+static int occ2(int persistent, size_t shm) {
     int n = 0;
-    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A, NB>
-                                : (const void*)k_mfma_grid<DT, A, NB>;
+    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, shm) != hipSuccess) return 1;
     return n;
 }
-template <int DT, int A>
-static int occ2(int nb, int persistent, size_t shm) {
-    if (nb <= 1) return occ3<DT, A, 1>(persistent, shm);
-    if (nb <= 2) return occ3<DT, A, 2>(persistent, shm);
-    return occ3<DT, A, 4>(persistent, shm);
-}
 template <int DT>
-static int occ1(int A, int nb, int persistent, size_t shm) {
-    if (A == 1) return occ2<DT, 1>(nb, persistent, shm);
-    if (A == 2) return occ2<DT, 2>(nb, persistent, shm);
-    return occ2<DT, 4>(nb, persistent, shm);
+static int occ1(int A, int persistent, size_t shm) {
+    if (A == 1) return occ2<DT, 1>(persistent, shm);
+    if (A == 2) return occ2<DT, 2>(persistent, shm);
+    return occ2<DT, 4>(persistent, shm);
 }
-int mfma_occupancy(int dt, int A, int nb, int persistent, size_t shm) {
+int mfma_occupancy(int dt, int A, int, int persistent, size_t shm) {
     switch (dt) {
-        case DT_BF16: return occ1<DT_BF16>(A, nb, persistent, shm);
-        case DT_FP16: return occ1<DT_FP16>(A, nb, persistent, shm);
-        case DT_BF16X3: return occ1<DT_BF16X3>(A, nb, persistent, shm);
-        case DT_FP8: return occ1<DT_FP8>(A, nb, persistent, shm);
+        case DT_BF16: return occ1<DT_BF16>(A, persistent, shm);
+        case DT_FP16: return occ1<DT_FP16>(A, persistent, shm);
+        case DT_BF16X3: return occ1<DT_BF16X3>(A, persistent, shm);
+        case DT_FP8: return occ1<DT_FP8>(A, persistent, shm);
         default: return 1;
     }
 }
