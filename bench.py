@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["bf16-hop1", "fp32-hop1", "bf16-hop512", "fp32-hop512"], default=None,
                     help="time one leg only (for profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -96,6 +98,15 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "launches": 5}))
+        return
     scales = synth.linear_scales(S)
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame

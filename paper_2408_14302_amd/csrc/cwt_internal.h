@@ -45,7 +45,7 @@ struct DirectGroup {
 // wave loads it with one coalesced access per lane.  BF16X3 stores the hi
 // fragment followed by the lo fragment.
 struct MfmaBlock {
-    int32_t lo, hi;        // K-step range (nested: all ranges are symmetric about 0)
+    int32_t lo, hi;        // K-step range; hi - lo + 1 is a multiple of 4 (zero-tap padding)
     int64_t frag_off;      // byte offset of step `lo` in the fragment buffer
     int32_t rows[kBlockRows];
     float inv_alpha[kBlockRows]; // FP8 only: 1/alpha_r; 1 otherwise

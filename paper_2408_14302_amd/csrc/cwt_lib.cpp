@@ -92,7 +92,9 @@ struct MfmaCfg {
     int A;
     int chunk;
 };
-static const MfmaCfg kMfmaCfgs[] = {{1, 8}, {2, 8}, {1, 16}, {2, 16}, {2, 4}, {4, 4}};
+// chunk is an upper bound (a multiple of 4); pick_chunk() shrinks it to what
+// the staging registers and the LDS budget hold for a given hop.
+static const MfmaCfg kMfmaCfgs[] = {{1, 64}, {2, 64}, {4, 32}, {1, 16}, {2, 16}, {4, 8}};
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 
 static int elem_bytes(int dt) { return dt == DT_FP8 ? 1 : 2; }
@@ -145,6 +147,28 @@ static Staging staging_for(int dt, int hop, int F, int chunk) {
         s.swz = -1;
     }
     return s;
+}
+
+// Largest chunk (multiple of 4, <= chunk_max) whose staging fits the kernel's
+// register prefetch (32 floats per thread, 256 threads) and 48 KiB of LDS for
+// the two buffers; 4 if none does (the kernel then stages the overflow
+// directly).  Mirrors the unit counts of stage_units() in mfma.hip.
+static int pick_chunk(int dt, int hop, int F, int chunk_max) {
+    const int U = 16 / elem_bytes(dt), KS = kstep_of(dt);
+    for (int chunk = chunk_max; chunk >= 4; chunk -= 4) {
+        Staging s = staging_for(dt, hop, F, chunk);
+        int64_t units, cap;
+        if (s.mode == STAGE_LINEAR) {
+            int64_t pmax = (int64_t)(F - 1) * hop + (int64_t)KS * chunk - 1;
+            units = ((pmax / U + 1) + 15) & ~int64_t(15);
+            cap = s.copies > 1 ? 256 * (32 / (2 * U)) : 256 * (32 / U);
+        } else {
+            units = (int64_t)F * (KS * chunk / U);
+            cap = 256 * (32 / U);
+        }
+        if (units <= cap && 2 * s.bytes <= 48 * 1024) return chunk;
+    }
+    return 4;
 }
 
 // ---------------------------------------------------------------------------
@@ -254,6 +278,9 @@ static cwt_status build_bank(int dt, int device, const std::vector<double>& scal
             // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb]
             B.lo = (int)std::floor(-(double)Mb / KS);
             B.hi = Mb / KS;
+            // whole groups of four steps (the extra steps hold zero taps), so the
+            // kernel's four-step K loop never ends inside a group
+            B.hi = B.lo + ((B.hi - B.lo + 1 + 3) / 4) * 4 - 1;
             B.frag_off = off;
             off += (int64_t)(B.hi - B.lo + 1) * step_bytes;
             bk->blocks.push_back(B);
@@ -365,7 +392,7 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     // FP8 scales the signal per 128-frame tile; a fixed tile keeps every clip's
     // result independent of the configuration and of the batch it runs in.
     if (p->dt == DT_FP8 && c.A != 1) return false;
-    Staging s = staging_for(p->dt, hop, 128 * c.A, c.chunk);
+    Staging s = staging_for(p->dt, hop, 128 * c.A, pick_chunk(p->dt, hop, 128 * c.A, c.chunk));
     return 2 * s.bytes <= mfma_max_lds_bytes() - 2048;
 }
 
@@ -414,10 +441,11 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
     a.blocks = bk.d_blocks;
     a.ngroups = (int)bk.blocks.size();
     a.signed_out = p->signed_out;
-    a.chunk_steps = c.chunk;
+    const int chunk = pick_chunk(p->dt, p->hop, F, c.chunk);
+    a.chunk_steps = chunk;
     a.frames = F;
     int64_t bytes = 0;
-    a.clip = make_clip(p, x, len, out, F, c.chunk, &bytes);
+    a.clip = make_clip(p, x, len, out, F, chunk, &bytes);
     a.buf_bytes = (int32_t)bytes;
     a.xcd_remap = 1;
     int64_t grid = (int64_t)a.clip.ntile * a.ngroups;
@@ -549,9 +577,12 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     // Longest first (most tiles first) so the persistent grid drains evenly.
     std::vector<ClipArg> clips(n);
     int64_t maxbytes = 16;
+    int chunk = c.chunk;
+    if (!fp32)
+        for (int i : order) chunk = std::min(chunk, pick_chunk(p0->dt, plans[i]->hop, F, c.chunk));
     for (int i : order) {
         int64_t bytes = 0;
-        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], F, c.chunk, &bytes);
+        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], F, chunk, &bytes);
         maxbytes = std::max(maxbytes, bytes);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return clips[a].ntile > clips[bq].ntile; });
@@ -593,7 +624,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.blocks = bk.d_blocks;
     a.ngroups = (int)bk.blocks.size();
     a.signed_out = p0->signed_out;
-    a.chunk_steps = c.chunk;
+    a.chunk_steps = chunk;
     a.frames = F;
     a.buf_bytes = (int32_t)maxbytes;
     a.xcd_remap = 0;
@@ -612,7 +643,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         // Kernel arguments that vary per batch (nclips, total tiles, prefix
         // address) are part of the captured node, so graphs are cached per
         // (shape) and their kernel node parameters refreshed before replay.
-        auto key = std::make_tuple(p0->dt, c.A, 1, (int)maxbytes, grid, c.chunk);
+        auto key = std::make_tuple(p0->dt, c.A, 1, (int)maxbytes, grid, chunk);
         GraphEntry& ge = b->graphs[key];
         if (!ge.exec) {
             HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");

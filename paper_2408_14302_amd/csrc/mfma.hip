@@ -150,15 +150,13 @@ __device__ __forceinline__ int swizzle(int unit, int swz) {
 // and written to LDS after them, so the global-load latency overlaps the
 // matrix work.  A LINEAR unit is a span of 2U floats that supplies one 16-byte
 // unit to every shifted copy; a ROWS unit is U floats of one frame's row.
-// Per-thread register budget of one prefetched chunk: one LINEAR span (2U floats).
+// Per-thread register budget of one prefetched chunk (floats).
 template <int DT>
-__device__ constexpr int stage_floats() { return 2 * Tr<DT>::U; }
+__device__ constexpr int stage_floats() { return 32; }
 
-template <int DT>
-__device__ constexpr int upt_linear() { return stage_floats<DT>() / (2 * Tr<DT>::U); }
-template <int DT>
-__device__ constexpr int upt_rows() { return stage_floats<DT>() / Tr<DT>::U; }
-
+// CNT samples x~[j .. j+CNT) into v[OFF ..]: float4 loads when the span is
+// inside [0, len) and 16-byte aligned, otherwise clamped scalar loads with the
+// out-of-range samples replaced by zero (no divergent branches).
 template <int CNT, int OFF, int N>
 __device__ __forceinline__ void load_span(const float* __restrict__ x, int64_t len, int64_t j,
                                           bool al16, float (&v)[N]) {
@@ -172,8 +170,10 @@ __device__ __forceinline__ void load_span(const float* __restrict__ x, int64_t l
     } else {
 #pragma unroll
         for (int e = 0; e < CNT; ++e) {
-            int64_t jj = j + e;
-            v[OFF + e] = (jj >= 0 && jj < len) ? x[jj] : 0.0f;
+            const int64_t jj = j + e;
+            const int64_t jc = jj < 0 ? 0 : (jj >= len ? len - 1 : jj);
+            const float t = x[jc];
+            v[OFF + e] = (jj >= 0 && jj < len) ? t : 0.0f;
         }
     }
 }
@@ -207,47 +207,86 @@ __device__ __forceinline__ void put_unit(uint8_t* lds, int off, int plane_bytes,
     for (int p = 0; p < Tr<DT>::PLANES; ++p) *(i32x4*)(lds + off + p * plane_bytes) = pk[p];
 }
 
-template <int DT, int I = 0>
-__device__ __forceinline__ void stage_load_lin(const ClipArg& c, const Geo& g, int64_t jb, bool al16,
-                                               float (&r)[2 * Tr<DT>::U]) {
-    constexpr int UP = upt_linear<DT>(), SP = 2 * Tr<DT>::U;
-    if constexpr (I < UP) {
-        const int uu = threadIdx.x + I * 256;
-        if (uu < g.len_u) load_span<SP, I * SP>(c.x, c.len, jb + (int64_t)uu * Tr<DT>::U, al16, r);
-        stage_load_lin<DT, I + 1>(c, g, jb, al16, r);
-    }
-}
-
-template <int DT, int I = 0>
-__device__ __forceinline__ void stage_load_rows(const ClipArg& c, int F, int per_row, int64_t k0, int ks_c,
-                                                bool al16, float (&r)[2 * Tr<DT>::U]) {
-    constexpr int UP = upt_rows<DT>(), SP = Tr<DT>::U;
-    if constexpr (I < UP) {
-        const int q = threadIdx.x + I * 256;
-        if (q < F * per_row) {
-            int f = q / per_row, cu = q - f * per_row;
-            int64_t j = (k0 + f) * c.hop + (int64_t)Tr<DT>::KS * ks_c + cu * Tr<DT>::U;
-            load_span<SP, I * SP>(c.x, c.len, j, al16, r);
-        }
-        stage_load_rows<DT, I + 1>(c, F, per_row, k0, ks_c, al16, r);
-    }
-}
+// Units of staging work.  A unit is one span of samples that one thread loads
+// and turns into 16-byte LDS units:
+//   LINEAR with copies > 1: 2U floats, one 16-byte unit for every copy;
+//   LINEAR with one copy, and ROWS: U floats, one 16-byte unit.
+template <int DT>
+__device__ __forceinline__ bool multi_copy(const Geo& g) { return g.mode == STAGE_LINEAR && g.copies > 1; }
 
 template <int DT>
-__device__ __forceinline__ void stage_load(const ClipArg& c, const Geo& g, int F, int chunk, int64_t k0,
-                                           int ks_c, bool al16, float (&r)[2 * Tr<DT>::U]) {
+__device__ __forceinline__ int stage_units(const Geo& g, int F, int chunk) {
     using T = Tr<DT>;
-    if (g.mode == STAGE_LINEAR)
-        stage_load_lin<DT>(c, g, k0 * c.hop + (int64_t)T::KS * ks_c, al16, r);
-    else
-        stage_load_rows<DT>(c, F, T::KS * chunk / T::U, k0, ks_c, al16, r);
+    return g.mode == STAGE_LINEAR ? g.len_u : F * (T::KS * chunk / T::U);
+}
+
+// Source sample of single-span unit q and its 16-byte LDS unit.
+template <int DT>
+__device__ __forceinline__ void unit_geo(const ClipArg& c, const Geo& g, int chunk, int64_t k0, int ks_c, int q,
+                                         int64_t& j, int& dst) {
+    using T = Tr<DT>;
+    if (g.mode == STAGE_LINEAR) {
+        j = k0 * c.hop + (int64_t)T::KS * ks_c + (int64_t)q * T::U;
+        dst = swizzle(q, g.swz);
+    } else {
+        const int per_row = T::KS * chunk / T::U;
+        const int f = q / per_row, cu = q - f * per_row;
+        j = (k0 + f) * c.hop + (int64_t)T::KS * ks_c + cu * T::U;
+        dst = f * g.rs + cu;
+    }
 }
 
 template <int DT, int I = 0>
-__device__ __forceinline__ void stage_store_lin(const Geo& g, float beta, const float (&r)[2 * Tr<DT>::U],
-                                                uint8_t* lds, int buf) {
-    constexpr int UP = upt_linear<DT>(), SP = 2 * Tr<DT>::U;
-    if constexpr (I < UP) {
+__device__ __forceinline__ void load_single(const ClipArg& c, const Geo& g, int chunk, int64_t k0, int ks_c,
+                                            int total, bool al16, float (&r)[stage_floats<DT>()]) {
+    constexpr int U = Tr<DT>::U;
+    if constexpr (I * U < stage_floats<DT>()) {
+        const int q = threadIdx.x + I * 256;
+        if (q < total) {
+            int64_t j;
+            int dst;
+            unit_geo<DT>(c, g, chunk, k0, ks_c, q, j, dst);
+            load_span<U, I * U>(c.x, c.len, j, al16, r);
+        }
+        load_single<DT, I + 1>(c, g, chunk, k0, ks_c, total, al16, r);
+    }
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void store_single(const ClipArg& c, const Geo& g, int chunk, int64_t k0, int ks_c,
+                                             int total, float beta, const float (&r)[stage_floats<DT>()],
+                                             uint8_t* lds, int buf) {
+    constexpr int U = Tr<DT>::U;
+    if constexpr (I * U < stage_floats<DT>()) {
+        const int q = threadIdx.x + I * 256;
+        if (q < total) {
+            int64_t j;
+            int dst;
+            unit_geo<DT>(c, g, chunk, k0, ks_c, q, j, dst);
+            i32x4 pk[Tr<DT>::PLANES];
+            pack_at<DT, I * U>(r, beta, pk);
+            put_unit<DT>(lds, buf + dst * 16, g.plane_bytes, pk);
+        }
+        store_single<DT, I + 1>(c, g, chunk, k0, ks_c, total, beta, r, lds, buf);
+    }
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void load_multi(const ClipArg& c, const Geo& g, int64_t jb, bool al16,
+                                           float (&r)[stage_floats<DT>()]) {
+    constexpr int SP = 2 * Tr<DT>::U;
+    if constexpr (I * SP < stage_floats<DT>()) {
+        const int uu = threadIdx.x + I * 256;
+        if (uu < g.len_u) load_span<SP, I * SP>(c.x, c.len, jb + (int64_t)uu * Tr<DT>::U, al16, r);
+        load_multi<DT, I + 1>(c, g, jb, al16, r);
+    }
+}
+
+template <int DT, int I = 0>
+__device__ __forceinline__ void store_multi(const Geo& g, float beta, const float (&r)[stage_floats<DT>()],
+                                            uint8_t* lds, int buf) {
+    constexpr int SP = 2 * Tr<DT>::U;
+    if constexpr (I * SP < stage_floats<DT>()) {
         const int uu = threadIdx.x + I * 256;
         if (uu < g.len_u) {
             const int su = swizzle(uu, g.swz);
@@ -257,40 +296,36 @@ __device__ __forceinline__ void stage_store_lin(const Geo& g, float beta, const 
                 put_unit<DT>(lds, buf + (cp * g.cs + su) * 16, g.plane_bytes, pk);
             }
         }
-        stage_store_lin<DT, I + 1>(g, beta, r, lds, buf);
+        store_multi<DT, I + 1>(g, beta, r, lds, buf);
     }
 }
 
-template <int DT, int I = 0>
-__device__ __forceinline__ void stage_store_rows(const Geo& g, int F, int per_row, float beta,
-                                                 const float (&r)[2 * Tr<DT>::U], uint8_t* lds, int buf) {
-    constexpr int UP = upt_rows<DT>(), SP = Tr<DT>::U;
-    if constexpr (I < UP) {
-        const int q = threadIdx.x + I * 256;
-        if (q < F * per_row) {
-            int f = q / per_row, cu = q - f * per_row;
-            i32x4 pk[Tr<DT>::PLANES];
-            pack_at<DT, I * SP>(r, beta, pk);
-            put_unit<DT>(lds, buf + (f * g.rs + cu) * 16, g.plane_bytes, pk);
-        }
-        stage_store_rows<DT, I + 1>(g, F, per_row, beta, r, lds, buf);
-    }
+// Issue the loads of a chunk's first units (as many as the register budget holds).
+template <int DT>
+__device__ __forceinline__ void stage_load(const ClipArg& c, const Geo& g, int F, int chunk, int64_t k0,
+                                           int ks_c, bool al16, float (&r)[stage_floats<DT>()]) {
+    using T = Tr<DT>;
+    if (multi_copy<DT>(g))
+        load_multi<DT>(c, g, k0 * c.hop + (int64_t)T::KS * ks_c, al16, r);
+    else
+        load_single<DT>(c, g, chunk, k0, ks_c, stage_units<DT>(g, F, chunk), al16, r);
 }
 
+// Convert and write the prefetched units, then stage any remaining units directly.
 template <int DT>
 __device__ __forceinline__ void stage_store(const ClipArg& c, const Geo& g, int F, int chunk, int64_t k0,
-                                            int ks_c, bool al16, float beta, const float (&r)[2 * Tr<DT>::U],
+                                            int ks_c, bool al16, float beta, const float (&r)[stage_floats<DT>()],
                                             uint8_t* lds, int buf) {
     using T = Tr<DT>;
+    constexpr int U = T::U;
     i32x4 pk[T::PLANES];
-    if (g.mode == STAGE_LINEAR) {
-        constexpr int UP = upt_linear<DT>(), SP = 2 * T::U;
-        stage_store_lin<DT>(g, beta, r, lds, buf);
-        // units beyond the register budget: load and store directly
+    if (multi_copy<DT>(g)) {
+        constexpr int SP = 2 * U, UP = stage_floats<DT>() / SP;
+        store_multi<DT>(g, beta, r, lds, buf);
         const int64_t jb = k0 * c.hop + (int64_t)T::KS * ks_c;
         for (int uu = threadIdx.x + UP * 256; uu < g.len_u; uu += 256) {
             float v[SP];
-            load_span<SP, 0>(c.x, c.len, jb + (int64_t)uu * T::U, al16, v);
+            load_span<SP, 0>(c.x, c.len, jb + (int64_t)uu * U, al16, v);
             const int su = swizzle(uu, g.swz);
             for (int cp = 0; cp < g.copies; ++cp) {
                 pack_shift<DT, 0>(v, cp * g.gh, beta, pk);
@@ -298,16 +333,17 @@ __device__ __forceinline__ void stage_store(const ClipArg& c, const Geo& g, int 
             }
         }
     } else {
-        constexpr int UP = upt_rows<DT>(), SP = T::U;
-        const int per_row = T::KS * chunk / T::U, total = F * per_row;
-        stage_store_rows<DT>(g, F, per_row, beta, r, lds, buf);
+        constexpr int UP = stage_floats<DT>() / U;
+        const int total = stage_units<DT>(g, F, chunk);
+        store_single<DT>(c, g, chunk, k0, ks_c, total, beta, r, lds, buf);
         for (int q = threadIdx.x + UP * 256; q < total; q += 256) {
-            int f = q / per_row, cu = q - f * per_row;
-            int64_t j = (k0 + f) * c.hop + (int64_t)T::KS * ks_c + cu * T::U;
-            float v[SP];
-            load_span<SP, 0>(c.x, c.len, j, al16, v);
+            int64_t j;
+            int dst;
+            unit_geo<DT>(c, g, chunk, k0, ks_c, q, j, dst);
+            float v[U];
+            load_span<U, 0>(c.x, c.len, j, al16, v);
             pack_at<DT, 0>(v, beta, pk);
-            put_unit<DT>(lds, buf + (f * g.rs + cu) * 16, g.plane_bytes, pk);
+            put_unit<DT>(lds, buf + dst * 16, g.plane_bytes, pk);
         }
     }
 }
@@ -394,17 +430,19 @@ __device__ __forceinline__ void mma_frags(const Frag<DT>& t, const Frag<DT> (&x)
     for (int fa = 0; fa < A; ++fa) acc[fa] = mma_all<DT>(t, x[fa], acc[fa]);
 }
 
-// K-loop of one tile for a fixed staging layout.  Per chunk: prefetch the next
-// chunk's samples into registers, run the chunk's steps two at a time with
-// ping-pong fragments (the next step's tap and signal fragments are in flight
-// while the current step's MFMAs issue), then write the prefetched samples to
-// the other LDS buffer and synchronise once.
+// K-loop of one tile for a fixed staging layout.  Per chunk: prefetch the
+// next chunk's samples into registers, run the chunk's steps four at a time,
+// then write the prefetched samples to the other LDS buffer and synchronise
+// once.  Tap fragments travel in a ring of four registers sets, loaded three
+// steps ahead (they come from L2); signal fragments in a ring of two, loaded
+// one step ahead (they come from LDS).  Chunks are multiples of four steps, so
+// the ring slot of a step is a compile-time constant.
 template <int DT, int A, int MODE>
 __device__ __forceinline__ void tile_loop(const MfmaArgs& a, const ClipArg& c, const Geo& g, int F, int64_t k0,
                                           int lo, int hi, const uint8_t* __restrict__ tbase, bool al16,
                                           float beta, uint8_t* lds, f32x16 (&acc)[A]) {
     using T = Tr<DT>;
-    const int chunk = a.chunk_steps;
+    const int chunk = a.chunk_steps;   // multiple of 4
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int n = lane & 31, hg = lane >> 5;
@@ -429,8 +467,10 @@ __device__ __forceinline__ void tile_loop(const MfmaArgs& a, const ClipArg& c, c
     float r[stage_floats<DT>()];
     stage_load<DT>(c, g, F, chunk, k0, lo, al16, r);
     stage_store<DT>(c, g, F, chunk, k0, lo, al16, beta, r, lds, 0);
-    Frag<DT> tA, tB, xA[A], xB[A];
-    load_tap<DT>(tap(lo), lane, tA);
+    Frag<DT> t0, t1, t2, t3, x0[A], x1[A];
+    load_tap<DT>(tap(lo), lane, t0);
+    load_tap<DT>(tap(lo + 1), lane, t1);
+    load_tap<DT>(tap(lo + 2), lane, t2);
     __syncthreads();
 
     for (int ci = 0; ci < nchunks; ++ci) {
@@ -439,20 +479,23 @@ __device__ __forceinline__ void tile_loop(const MfmaArgs& a, const ClipArg& c, c
         const int buf = (ci & 1) * a.buf_bytes;
         const bool more = ci + 1 < nchunks;
         if (more) stage_load<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, r);
-        load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, 0, xA);
-        int d = 0;
-        for (; d + 1 < ns; d += 2) {
-            load_tap<DT>(tap(ks_c + d + 1), lane, tB);
-            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, d + 1, xB);
-            mma_frags<DT, A>(tA, xA, acc);
-            load_tap<DT>(tap(ks_c + d + 2), lane, tA);
-            if (d + 2 < ns) load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, d + 2, xA);
-            mma_frags<DT, A>(tB, xB, acc);
-        }
-        if (d < ns) {                      // odd step count: the last step
-            load_tap<DT>(tap(ks_c + d + 1), lane, tB);
-            mma_frags<DT, A>(tA, xA, acc);
-            tA = tB;
+        load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, 0, x0);
+        // ns is a multiple of 4: block ranges are padded to whole groups of four steps.
+        for (int q = 0; q < ns; q += 4) {
+            const int s = ks_c + q;
+            const bool last = q + 4 >= ns;        // the next chunk's buffer is not ready yet
+            load_tap<DT>(tap(s + 3), lane, t3);
+            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 1, x1);
+            mma_frags<DT, A>(t0, x0, acc);
+            load_tap<DT>(tap(s + 4), lane, t0);
+            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 2, x0);
+            mma_frags<DT, A>(t1, x1, acc);
+            load_tap<DT>(tap(s + 5), lane, t1);
+            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 3, x1);
+            mma_frags<DT, A>(t2, x0, acc);
+            load_tap<DT>(tap(s + 6), lane, t2);
+            if (!last) load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 4, x0);
+            mma_frags<DT, A>(t3, x1, acc);
         }
         if (more) stage_store<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, beta, r, lds, ((ci + 1) & 1) * a.buf_bytes);
         __syncthreads();
