@@ -45,7 +45,7 @@ struct DirectGroup {
 // wave loads it with one coalesced access per lane.  BF16X3 stores the hi
 // fragment followed by the lo fragment.
 struct MfmaBlock {
-    int32_t lo, hi;        // K-step range; hi - lo + 1 is a multiple of 4 (zero-tap padding)
+    int32_t lo, hi;        // K-step range; hi - lo + 1 is a multiple of 8 (zero-tap padding)
     int64_t frag_off;      // byte offset of step `lo` in the fragment buffer
     int32_t rows[kBlockRows];
     float inv_alpha[kBlockRows]; // FP8 only: 1/alpha_r; 1 otherwise
@@ -75,9 +75,10 @@ struct MfmaArgs {
     const MfmaBlock* blocks;
     int32_t ngroups;       // number of 32-scale blocks (one per work-group tile)
     int32_t signed_out;
-    int32_t chunk_steps;   // K-steps staged per LDS chunk
+    int32_t chunk_steps;   // K-steps staged per LDS chunk (a multiple of 8)
     int32_t frames;        // frames per tile (= 32 * A * kMfmaWaves)
-    int32_t buf_bytes;     // bytes of one LDS staging buffer
+    int32_t buf_bytes;     // bytes of one LDS staging buffer (two are used)
+    int32_t raw_bytes;     // bytes of the raw FP32 window buffer (linear staging)
     int32_t xcd_remap;     // 1: map consecutive tiles to the same XCD
     // single clip (grid launch)
     ClipArg clip;

@@ -94,7 +94,7 @@ struct MfmaCfg {
 };
 // chunk is an upper bound (a multiple of 4); pick_chunk() shrinks it to what
 // the staging registers and the LDS budget hold for a given hop.
-static const MfmaCfg kMfmaCfgs[] = {{1, 64}, {2, 64}, {4, 32}, {1, 16}, {2, 16}, {4, 8}};
+static const MfmaCfg kMfmaCfgs[] = {{1, 64}, {2, 64}, {4, 32}, {1, 16}, {2, 16}, {4, 16}};
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 
 static int elem_bytes(int dt) { return dt == DT_FP8 ? 1 : 2; }
@@ -112,7 +112,8 @@ static int64_t gcd64(int64_t a, int64_t b) {
 // Staging geometry of one clip for the MFMA kernel; mirrors make_geo() in mfma.hip.
 struct Staging {
     int mode, copies, swz;
-    int64_t bytes;  // one LDS buffer (all planes)
+    int64_t bytes;      // one LDS operand buffer (all planes); two are used
+    int64_t raw_bytes;  // LINEAR: the raw FP32 window buffer
 };
 
 static Staging staging_for(int dt, int hop, int F, int chunk) {
@@ -141,34 +142,34 @@ static Staging staging_for(int dt, int hop, int F, int chunk) {
     if (lin <= rows && !lin_conflicts) {
         s.mode = STAGE_LINEAR;
         s.bytes = lin;
+        s.raw_bytes = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;   // raw_floats() in mfma.hip
     } else {
         s.mode = STAGE_ROWS;
         s.bytes = rows;
         s.swz = -1;
+        s.raw_bytes = 0;
     }
     return s;
 }
 
-// Largest chunk (multiple of 4, <= chunk_max) whose staging fits the kernel's
-// register prefetch (32 floats per thread, 256 threads) and 48 KiB of LDS for
-// the two buffers; 4 if none does (the kernel then stages the overflow
-// directly).  Mirrors the unit counts of stage_units() in mfma.hip.
+// Largest chunk (multiple of 8, <= chunk_max) whose LDS (two operand buffers
+// plus the raw window) fits kLdsBudget and, for the row layout, whose units fit
+// the kernel's register prefetch (32 floats per thread, 256 threads); 8 if none
+// does (the kernel then stages the overflow directly).
+static const int64_t kLdsBudget = 52 * 1024;   // three work-groups per CU
 static int pick_chunk(int dt, int hop, int F, int chunk_max) {
     const int U = 16 / elem_bytes(dt), KS = kstep_of(dt);
-    for (int chunk = chunk_max; chunk >= 4; chunk -= 4) {
+    for (int chunk = chunk_max; chunk >= 8; chunk -= 8) {
         Staging s = staging_for(dt, hop, F, chunk);
-        int64_t units, cap;
+        const int64_t lds = 2 * s.bytes + s.raw_bytes;
         if (s.mode == STAGE_LINEAR) {
-            int64_t pmax = (int64_t)(F - 1) * hop + (int64_t)KS * chunk - 1;
-            units = ((pmax / U + 1) + 15) & ~int64_t(15);
-            cap = s.copies > 1 ? 256 * (32 / (2 * U)) : 256 * (32 / U);
+            if (lds <= kLdsBudget) return chunk;       // the conversion pass has no register limit
         } else {
-            units = (int64_t)F * (KS * chunk / U);
-            cap = 256 * (32 / U);
+            const int64_t units = (int64_t)F * (KS * chunk / U), cap = 256 * (32 / U);
+            if (units <= cap && lds <= kLdsBudget) return chunk;
         }
-        if (units <= cap && 2 * s.bytes <= 48 * 1024) return chunk;
     }
-    return 4;
+    return 8;
 }
 
 // ---------------------------------------------------------------------------
@@ -278,9 +279,9 @@ static cwt_status build_bank(int dt, int device, const std::vector<double>& scal
             // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb]
             B.lo = (int)std::floor(-(double)Mb / KS);
             B.hi = Mb / KS;
-            // whole groups of four steps (the extra steps hold zero taps), so the
-            // kernel's four-step K loop never ends inside a group
-            B.hi = B.lo + ((B.hi - B.lo + 1 + 3) / 4) * 4 - 1;
+            // whole groups of eight steps (the extra steps hold zero taps), so the
+            // kernel's eight-step K loop never ends inside a group
+            B.hi = B.lo + ((B.hi - B.lo + 1 + 7) / 8) * 8 - 1;
             B.frag_off = off;
             off += (int64_t)(B.hi - B.lo + 1) * step_bytes;
             bk->blocks.push_back(B);
@@ -382,7 +383,7 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
 
 static int default_cfg(int dt, int hop) {
     if (dt == DT_FP32 || dt == DT_FP8) return 0;
-    return hop <= 64 ? 1 : 0;   // {2,8} for small hops, {1,8} otherwise
+    return hop <= 8 ? 2 : (hop <= 64 ? 1 : 0);   // A = 4 / 2 / 1 as the hop grows
 }
 
 static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
@@ -393,13 +394,13 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     // result independent of the configuration and of the batch it runs in.
     if (p->dt == DT_FP8 && c.A != 1) return false;
     Staging s = staging_for(p->dt, hop, 128 * c.A, pick_chunk(p->dt, hop, 128 * c.A, c.chunk));
-    return 2 * s.bytes <= mfma_max_lds_bytes() - 2048;
+    return 2 * s.bytes + s.raw_bytes <= mfma_max_lds_bytes() - 2048;
 }
 
 // ---------------------------------------------------------------------------
 // Launch of one clip.
 static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int F,
-                         int chunk, int64_t* bytes_out) {
+                         int chunk, int64_t* bytes_out, int64_t* raw_out = nullptr) {
     ClipArg c;
     std::memset(&c, 0, sizeof(c));
     c.x = x;
@@ -414,6 +415,7 @@ static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float
         c.copies = s.copies;
         c.swz = s.swz;
         if (bytes_out) *bytes_out = s.bytes;
+        if (raw_out) *raw_out = s.raw_bytes;
     }
     return c;
 }
@@ -444,9 +446,10 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
     const int chunk = pick_chunk(p->dt, p->hop, F, c.chunk);
     a.chunk_steps = chunk;
     a.frames = F;
-    int64_t bytes = 0;
-    a.clip = make_clip(p, x, len, out, F, chunk, &bytes);
+    int64_t bytes = 0, raw = 0;
+    a.clip = make_clip(p, x, len, out, F, chunk, &bytes, &raw);
     a.buf_bytes = (int32_t)bytes;
+    a.raw_bytes = (int32_t)raw;
     a.xcd_remap = 1;
     int64_t grid = (int64_t)a.clip.ntile * a.ngroups;
     if (grid > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
@@ -580,10 +583,12 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     int chunk = c.chunk;
     if (!fp32)
         for (int i : order) chunk = std::min(chunk, pick_chunk(p0->dt, plans[i]->hop, F, c.chunk));
+    int64_t maxraw = 0;
     for (int i : order) {
-        int64_t bytes = 0;
-        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], F, chunk, &bytes);
+        int64_t bytes = 0, raw = 0;
+        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], F, chunk, &bytes, &raw);
         maxbytes = std::max(maxbytes, bytes);
+        maxraw = std::max(maxraw, raw);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return clips[a].ntile > clips[bq].ntile; });
     const int nc = (int)order.size();
@@ -627,6 +632,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.chunk_steps = chunk;
     a.frames = F;
     a.buf_bytes = (int32_t)maxbytes;
+    a.raw_bytes = (int32_t)maxraw;
     a.xcd_remap = 0;
     // The descriptor pointers are fixed device addresses; counts live in the header.
     a.clips = (const ClipArg*)(b->d_desc + 16);
@@ -634,7 +640,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.nclips = nc;
     a.total_tiles = (int32_t)total;
     a.counter = b->d_counter;
-    const int grid = persistent_grid(b->cus, p0->dt, c.A, 1, 2 * maxbytes);
+    const int grid = persistent_grid(b->cus, p0->dt, c.A, 1, 2 * maxbytes + maxraw);
 
     if (!use_graph) {
         HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
@@ -643,7 +649,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         // Kernel arguments that vary per batch (nclips, total tiles, prefix
         // address) are part of the captured node, so graphs are cached per
         // (shape) and their kernel node parameters refreshed before replay.
-        auto key = std::make_tuple(p0->dt, c.A, 1, (int)maxbytes, grid, chunk);
+        auto key = std::make_tuple(p0->dt, c.A, (int)maxraw, (int)maxbytes, grid, chunk);
         GraphEntry& ge = b->graphs[key];
         if (!ge.exec) {
             HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");

@@ -150,9 +150,6 @@ __device__ __forceinline__ int swizzle(int unit, int swz) {
 // and written to LDS after them, so the global-load latency overlaps the
 // matrix work.  A LINEAR unit is a span of 2U floats that supplies one 16-byte
 // unit to every shifted copy; a ROWS unit is U floats of one frame's row.
-// Per-thread register budget of one prefetched chunk (floats).
-template <int DT>
-__device__ constexpr int stage_floats() { return 32; }
 
 // CNT samples x~[j .. j+CNT) into v[OFF ..]: float4 loads when the span is
 // inside [0, len) and 16-byte aligned, otherwise clamped scalar loads with the
@@ -178,27 +175,59 @@ __device__ __forceinline__ void load_span(const float* __restrict__ x, int64_t l
     }
 }
 
-// pack_unit of v[OFF+sh .. OFF+sh+U-1] for a run-time shift sh in [0, U) (uniform).
-template <int DT, int OFF, int N, int S = 0>
-__device__ __forceinline__ void pack_shift(const float (&v)[N], int sh, float beta, i32x4* pk) {
-    if constexpr (S < Tr<DT>::U) {
-        if (sh == S) {
-            float t[Tr<DT>::U];
+// ---------------------------------------------------------------------------
+// Packing.  A span of CNT samples is converted once into packed operand
+// dwords (per plane); a 16-byte LDS unit that starts SH elements into the span
+// is then four funnel shifts (v_alignbyte) of those dwords.
+template <int DT, int CNT>
+struct Packed {
+    static constexpr int ND = CNT * Tr<DT>::ES / 4;   // dwords per plane
+    uint32_t d[Tr<DT>::PLANES][ND];
+};
+
+template <int DT, int CNT, int OFF, int N>
+__device__ __forceinline__ void pack_span(const float (&v)[N], float beta, Packed<DT, CNT>& pk) {
+    if constexpr (DT == DT_BF16 || DT == DT_BF16X3) {
 #pragma unroll
-            for (int e = 0; e < Tr<DT>::U; ++e) t[e] = v[OFF + S + e];
-            pack_unit<DT>(t, beta, pk);
-            return;
+        for (int i = 0; i < CNT / 2; ++i) {
+            const float a0 = v[OFF + 2 * i], a1 = v[OFF + 2 * i + 1];
+            const __bf16 h0 = (__bf16)a0, h1 = (__bf16)a1;
+            pk.d[0][i] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            if constexpr (DT == DT_BF16X3) {
+                const __bf16 l0 = (__bf16)(a0 - (float)h0), l1 = (__bf16)(a1 - (float)h1);   // exact residuals
+                pk.d[1][i] = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+            }
         }
-        pack_shift<DT, OFF, N, S + 1>(v, sh, beta, pk);
+    } else if constexpr (DT == DT_FP16) {
+#pragma unroll
+        for (int i = 0; i < CNT / 2; ++i) {
+            const _Float16 h0 = (_Float16)v[OFF + 2 * i], h1 = (_Float16)v[OFF + 2 * i + 1];
+            pk.d[0][i] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < CNT / 4; ++i) {
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[OFF + 4 * i] * beta, v[OFF + 4 * i + 1] * beta, 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(v[OFF + 4 * i + 2] * beta, v[OFF + 4 * i + 3] * beta, w, true);
+            pk.d[0][i] = (uint32_t)w;
+        }
     }
 }
 
-template <int DT, int OFF, int N>
-__device__ __forceinline__ void pack_at(const float (&v)[N], float beta, i32x4* pk) {
-    float t[Tr<DT>::U];
+// 16 bytes of plane p starting SH elements into the packed span.
+template <int DT, int CNT, int SH>
+__device__ __forceinline__ i32x4 window(const Packed<DT, CNT>& pk, int p) {
+    constexpr int B = SH * Tr<DT>::ES, q = B / 4, r = B % 4;
+    static_assert(q + 4 + (r ? 1 : 0) <= Packed<DT, CNT>::ND, "window outside the span");
+    i32x4 o;
 #pragma unroll
-    for (int e = 0; e < Tr<DT>::U; ++e) t[e] = v[OFF + e];
-    pack_unit<DT>(t, beta, pk);
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (r == 0)
+            o[i] = (int)pk.d[p][q + i];
+        else
+            o[i] = (int)__builtin_amdgcn_alignbyte(pk.d[p][q + i + 1], pk.d[p][q + i], r);
+    }
+    return o;
 }
 
 template <int DT>
@@ -207,10 +236,28 @@ __device__ __forceinline__ void put_unit(uint8_t* lds, int off, int plane_bytes,
     for (int p = 0; p < Tr<DT>::PLANES; ++p) *(i32x4*)(lds + off + p * plane_bytes) = pk[p];
 }
 
+// Write the copies of one multi-copy unit: copy cp is the window at SH = cp*gh.
+template <int DT, int CNT, int SH = 0>
+__device__ __forceinline__ void put_copies(const Packed<DT, CNT>& pk, const Geo& g, int su, uint8_t* lds, int buf) {
+    if constexpr (SH < Tr<DT>::U) {
+        if (SH % g.gh == 0) {
+            i32x4 u[Tr<DT>::PLANES];
+#pragma unroll
+            for (int p = 0; p < Tr<DT>::PLANES; ++p) u[p] = window<DT, CNT, SH>(pk, p);
+            put_unit<DT>(lds, buf + ((SH / g.gh) * g.cs + su) * 16, g.plane_bytes, u);
+        }
+        put_copies<DT, CNT, SH + 1>(pk, g, su, lds, buf);
+    }
+}
+
 // Units of staging work.  A unit is one span of samples that one thread loads
 // and turns into 16-byte LDS units:
-//   LINEAR with copies > 1: 2U floats, one 16-byte unit for every copy;
-//   LINEAR with one copy, and ROWS: U floats, one 16-byte unit.
+//   LINEAR with copies > 1: 2U samples, one 16-byte unit for every copy;
+//   LINEAR with one copy, and ROWS: U samples, one 16-byte unit.
+// Per-thread register budget of one prefetched chunk (floats).
+template <int DT>
+__device__ constexpr int stage_floats() { return 32; }
+
 template <int DT>
 __device__ __forceinline__ bool multi_copy(const Geo& g) { return g.mode == STAGE_LINEAR && g.copies > 1; }
 
@@ -240,7 +287,7 @@ template <int DT, int I = 0>
 __device__ __forceinline__ void load_single(const ClipArg& c, const Geo& g, int chunk, int64_t k0, int ks_c,
                                             int total, bool al16, float (&r)[stage_floats<DT>()]) {
     constexpr int U = Tr<DT>::U;
-    if constexpr (I * U < stage_floats<DT>()) {
+    if constexpr ((I + 1) * U <= stage_floats<DT>()) {
         const int q = threadIdx.x + I * 256;
         if (q < total) {
             int64_t j;
@@ -257,15 +304,18 @@ __device__ __forceinline__ void store_single(const ClipArg& c, const Geo& g, int
                                              int total, float beta, const float (&r)[stage_floats<DT>()],
                                              uint8_t* lds, int buf) {
     constexpr int U = Tr<DT>::U;
-    if constexpr (I * U < stage_floats<DT>()) {
+    if constexpr ((I + 1) * U <= stage_floats<DT>()) {
         const int q = threadIdx.x + I * 256;
         if (q < total) {
             int64_t j;
             int dst;
             unit_geo<DT>(c, g, chunk, k0, ks_c, q, j, dst);
-            i32x4 pk[Tr<DT>::PLANES];
-            pack_at<DT, I * U>(r, beta, pk);
-            put_unit<DT>(lds, buf + dst * 16, g.plane_bytes, pk);
+            Packed<DT, U> pk;
+            pack_span<DT, U, I * U>(r, beta, pk);
+            i32x4 u[Tr<DT>::PLANES];
+#pragma unroll
+            for (int p = 0; p < Tr<DT>::PLANES; ++p) u[p] = window<DT, U, 0>(pk, p);
+            put_unit<DT>(lds, buf + dst * 16, g.plane_bytes, u);
         }
         store_single<DT, I + 1>(c, g, chunk, k0, ks_c, total, beta, r, lds, buf);
     }
@@ -275,7 +325,7 @@ template <int DT, int I = 0>
 __device__ __forceinline__ void load_multi(const ClipArg& c, const Geo& g, int64_t jb, bool al16,
                                            float (&r)[stage_floats<DT>()]) {
     constexpr int SP = 2 * Tr<DT>::U;
-    if constexpr (I * SP < stage_floats<DT>()) {
+    if constexpr ((I + 1) * SP <= stage_floats<DT>()) {
         const int uu = threadIdx.x + I * 256;
         if (uu < g.len_u) load_span<SP, I * SP>(c.x, c.len, jb + (int64_t)uu * Tr<DT>::U, al16, r);
         load_multi<DT, I + 1>(c, g, jb, al16, r);
@@ -286,17 +336,91 @@ template <int DT, int I = 0>
 __device__ __forceinline__ void store_multi(const Geo& g, float beta, const float (&r)[stage_floats<DT>()],
                                             uint8_t* lds, int buf) {
     constexpr int SP = 2 * Tr<DT>::U;
-    if constexpr (I * SP < stage_floats<DT>()) {
+    if constexpr ((I + 1) * SP <= stage_floats<DT>()) {
         const int uu = threadIdx.x + I * 256;
         if (uu < g.len_u) {
-            const int su = swizzle(uu, g.swz);
-            i32x4 pk[Tr<DT>::PLANES];
-            for (int cp = 0; cp < g.copies; ++cp) {
-                pack_shift<DT, I * SP>(r, cp * g.gh, beta, pk);
-                put_unit<DT>(lds, buf + (cp * g.cs + su) * 16, g.plane_bytes, pk);
-            }
+            Packed<DT, SP> pk;
+            pack_span<DT, SP, I * SP>(r, beta, pk);
+            put_copies<DT, SP>(pk, g, swizzle(uu, g.swz), lds, buf);
         }
         store_multi<DT, I + 1>(g, beta, r, lds, buf);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LINEAR staging through a raw FP32 window in LDS.  raw[p] = x~[jb + p] for
+// p < raw_floats(): whole float4s that lie inside [0, len) arrive by direct
+// global-to-LDS loads (no registers held across the MFMAs); the conversion
+// pass then builds the operand copies from LDS, reading the few float4s that
+// straddle the clip edges from global memory with clamped loads.
+template <int DT>
+__device__ __forceinline__ int raw_floats(const Geo& g) {
+    return ((g.len_u + 1) * Tr<DT>::U + 255) & ~255;
+}
+
+__device__ __forceinline__ bool float4_direct(int64_t j, int64_t len, bool al16) {
+    return al16 && j >= 0 && j + 4 <= len;
+}
+
+template <int DT>
+__device__ __forceinline__ void raw_issue(const ClipArg& c, const Geo& g, int64_t jb, bool al16, uint8_t* raw) {
+    const int nv = raw_floats<DT>(g) / 4;            // float4s, a multiple of 64
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int v0 = w * 64; v0 < nv; v0 += 256) {     // one wave instruction covers 64 float4s
+        const int64_t j = jb + 4 * (int64_t)(v0 + lane);
+        if (float4_direct(j, c.len, al16))
+            __builtin_amdgcn_global_load_lds((const void*)(c.x + j),
+                                             (__attribute__((address_space(3))) void*)(raw + v0 * 16), 16, 0, 0);
+    }
+}
+
+// CNT raw samples starting at p (a multiple of 4) into v[OFF ..].
+template <int CNT, int OFF, int N>
+__device__ __forceinline__ void raw_span(const ClipArg& c, int64_t jb, bool al16, const uint8_t* raw, int p,
+                                         float (&v)[N]) {
+#pragma unroll
+    for (int e = 0; e < CNT; e += 4) {
+        const int64_t j = jb + p + e;
+        if (float4_direct(j, c.len, al16)) {
+            const float4 f4 = *(const float4*)(raw + (p + e) * 4);
+            v[OFF + e] = f4.x; v[OFF + e + 1] = f4.y; v[OFF + e + 2] = f4.z; v[OFF + e + 3] = f4.w;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t jj = j + i;
+                const int64_t jc = jj < 0 ? 0 : (jj >= c.len ? c.len - 1 : jj);
+                const float t = c.x[jc];
+                v[OFF + e + i] = (jj >= 0 && jj < c.len) ? t : 0.0f;
+            }
+        }
+    }
+}
+
+// Raw window -> operand copies in LDS buffer `buf`.
+template <int DT>
+__device__ __forceinline__ void raw_convert(const ClipArg& c, const Geo& g, int64_t jb, bool al16, float beta,
+                                            const uint8_t* raw, uint8_t* lds, int buf) {
+    constexpr int U = Tr<DT>::U;
+    if (g.copies > 1) {
+        constexpr int SP = 2 * U;
+        for (int uu = threadIdx.x; uu < g.len_u; uu += 256) {
+            float v[SP];
+            raw_span<SP, 0>(c, jb, al16, raw, uu * U, v);
+            Packed<DT, SP> pk;
+            pack_span<DT, SP, 0>(v, beta, pk);
+            put_copies<DT, SP>(pk, g, swizzle(uu, g.swz), lds, buf);
+        }
+    } else {
+        for (int uu = threadIdx.x; uu < g.len_u; uu += 256) {
+            float v[U];
+            raw_span<U, 0>(c, jb, al16, raw, uu * U, v);
+            Packed<DT, U> pk;
+            pack_span<DT, U, 0>(v, beta, pk);
+            i32x4 u[Tr<DT>::PLANES];
+#pragma unroll
+            for (int p = 0; p < Tr<DT>::PLANES; ++p) u[p] = window<DT, U, 0>(pk, p);
+            put_unit<DT>(lds, buf + swizzle(uu, g.swz) * 16, g.plane_bytes, u);
+        }
     }
 }
 
@@ -318,7 +442,6 @@ __device__ __forceinline__ void stage_store(const ClipArg& c, const Geo& g, int 
                                             uint8_t* lds, int buf) {
     using T = Tr<DT>;
     constexpr int U = T::U;
-    i32x4 pk[T::PLANES];
     if (multi_copy<DT>(g)) {
         constexpr int SP = 2 * U, UP = stage_floats<DT>() / SP;
         store_multi<DT>(g, beta, r, lds, buf);
@@ -326,11 +449,9 @@ __device__ __forceinline__ void stage_store(const ClipArg& c, const Geo& g, int 
         for (int uu = threadIdx.x + UP * 256; uu < g.len_u; uu += 256) {
             float v[SP];
             load_span<SP, 0>(c.x, c.len, jb + (int64_t)uu * U, al16, v);
-            const int su = swizzle(uu, g.swz);
-            for (int cp = 0; cp < g.copies; ++cp) {
-                pack_shift<DT, 0>(v, cp * g.gh, beta, pk);
-                put_unit<DT>(lds, buf + (cp * g.cs + su) * 16, g.plane_bytes, pk);
-            }
+            Packed<DT, SP> pk;
+            pack_span<DT, SP, 0>(v, beta, pk);
+            put_copies<DT, SP>(pk, g, swizzle(uu, g.swz), lds, buf);
         }
     } else {
         constexpr int UP = stage_floats<DT>() / U;
@@ -342,8 +463,12 @@ __device__ __forceinline__ void stage_store(const ClipArg& c, const Geo& g, int 
             unit_geo<DT>(c, g, chunk, k0, ks_c, q, j, dst);
             float v[U];
             load_span<U, 0>(c.x, c.len, j, al16, v);
-            pack_at<DT, 0>(v, beta, pk);
-            put_unit<DT>(lds, buf + dst * 16, g.plane_bytes, pk);
+            Packed<DT, U> pk;
+            pack_span<DT, U, 0>(v, beta, pk);
+            i32x4 u[T::PLANES];
+#pragma unroll
+            for (int p = 0; p < T::PLANES; ++p) u[p] = window<DT, U, 0>(pk, p);
+            put_unit<DT>(lds, buf + dst * 16, g.plane_bytes, u);
         }
     }
 }
@@ -400,26 +525,31 @@ __device__ __forceinline__ void load_tap(const uint8_t* __restrict__ tp, int lan
         for (int u = 0; u < T::LU; ++u) t.u[p][u] = *((const i32x4*)(p0 + p * 64 * T::FRAG) + u);
 }
 
+// Staging layouts as seen by the K loop: linear window without swizzle (every
+// read is a per-lane base plus an immediate offset), linear window with the
+// XOR swizzle (power-of-two hops), or one row per frame.
+enum LoopMode : int { LM_LINEAR = 0, LM_LINEAR_SWZ = 1, LM_ROWS = 2 };
+
 // Signal fragments of step d (relative to the chunk's first step) for the
-// lane's A frame blocks.  LINEAR: copy base + swizzled unit; ROWS: row base + unit.
-template <int DT, int A, int MODE>
-__device__ __forceinline__ void load_x(const uint8_t* lds, int buf, int plane_bytes, int swz,
-                                       const int (&base)[A], const int (&unit0)[A], int d, Frag<DT> (&x)[A]) {
+// lane's A frame blocks.  `vb[fa]` is the lane's byte offset of step 0.
+template <int DT, int A, int LM>
+__device__ __forceinline__ void load_x(const uint8_t* lds, int plane_bytes, int swz, const int (&vb)[A],
+                                       const int (&unit0)[A], int d, Frag<DT> (&x)[A]) {
     using T = Tr<DT>;
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
 #pragma unroll
         for (int u = 0; u < T::LU; ++u) {
             int off;
-            if constexpr (MODE == STAGE_LINEAR) {
+            if constexpr (LM == LM_LINEAR_SWZ) {
                 const int unit = unit0[fa] + d * (T::KS / T::U) + u;
-                off = base[fa] + ((unit ^ ((unit >> swz) & 15)) << 4);
+                off = vb[fa] + ((unit ^ ((unit >> swz) & 15)) << 4);
             } else {
-                off = base[fa] + ((d * (T::KS / T::U) + u) << 4);
+                off = vb[fa] + ((d * (T::KS / T::U) + u) << 4);
             }
 #pragma unroll
             for (int p = 0; p < T::PLANES; ++p)
-                x[fa].u[p][u] = *(const i32x4*)(lds + buf + p * plane_bytes + off);
+                x[fa].u[p][u] = *(const i32x4*)(lds + p * plane_bytes + off);
         }
     }
 }
@@ -430,73 +560,136 @@ __device__ __forceinline__ void mma_frags(const Frag<DT>& t, const Frag<DT> (&x)
     for (int fa = 0; fa < A; ++fa) acc[fa] = mma_all<DT>(t, x[fa], acc[fa]);
 }
 
-// K-loop of one tile for a fixed staging layout.  Per chunk: prefetch the
-// next chunk's samples into registers, run the chunk's steps four at a time,
-// then write the prefetched samples to the other LDS buffer and synchronise
-// once.  Tap fragments travel in a ring of four registers sets, loaded three
-// steps ahead (they come from L2); signal fragments in a ring of two, loaded
-// one step ahead (they come from LDS).  Chunks are multiples of four steps, so
-// the ring slot of a step is a compile-time constant.
-template <int DT, int A, int MODE>
-__device__ __forceinline__ void tile_loop(const MfmaArgs& a, const ClipArg& c, const Geo& g, int F, int64_t k0,
-                                          int lo, int hi, const uint8_t* __restrict__ tbase, bool al16,
-                                          float beta, uint8_t* lds, f32x16 (&acc)[A]) {
+// Per-lane LDS byte offset of step 0 of a chunk (within one buffer) and, for
+// the swizzled layout, the logical 16-byte unit of step 0.
+template <int DT, int A, int LM>
+__device__ __forceinline__ void lane_bases(const ClipArg& c, const Geo& g, int (&base)[A], int (&unit0)[A]) {
     using T = Tr<DT>;
-    const int chunk = a.chunk_steps;   // multiple of 4
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane & 31, hg = lane >> 5;
-    const int swz = g.swz < 0 ? 31 : g.swz;        // 31: unit >> 31 == 0, no swizzle
-
-    int base[A], unit0[A];
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
         const int f = 32 * (A * w + fa) + n;
-        if constexpr (MODE == STAGE_LINEAR) {
-            const int p = f * c.hop + hg * T::PER;
-            base[fa] = ((p % T::U) / g.gh) * g.cs * 16;
-            unit0[fa] = p / T::U;
-        } else {
+        if constexpr (LM == LM_ROWS) {
             base[fa] = (f * g.rs + hg * T::LU) * 16;
             unit0[fa] = 0;
+        } else {
+            const int p = f * c.hop + hg * T::PER;
+            const int cbase = ((p % T::U) / g.gh) * g.cs * 16;
+            unit0[fa] = p / T::U;
+            base[fa] = LM == LM_LINEAR ? cbase + unit0[fa] * 16 : cbase;
         }
     }
+}
+
+// The MFMAs of one chunk (ns steps, a multiple of 8) from LDS buffer `cur`.
+// Tap fragments (from L2) are loaded eight steps ahead into two banks of four
+// register sets, signal fragments (from LDS) one step ahead into a ring of two;
+// every slot is a compile-time constant.
+template <int DT, int A, int LM>
+__device__ __forceinline__ void compute_chunk(const uint8_t* cur, const Geo& g, int swz, const int (&base)[A],
+                                              const int (&unit0)[A], int ks_c, int ns, int hi, int lo,
+                                              const uint8_t* __restrict__ tbase, Frag<DT> (&ta)[4],
+                                              Frag<DT> (&tb)[4], f32x16 (&acc)[A]) {
+    using T = Tr<DT>;
+    const int lane = threadIdx.x & 63;
+    auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
+    Frag<DT> x0[A], x1[A];
+    load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, 0, x0);
+    for (int q = 0; q < ns; q += 8) {
+        const int s8 = ks_c + q;
+        const bool last = q + 8 >= ns;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            Frag<DT>& tcur = j < 4 ? ta[j & 3] : tb[j & 3];
+            if ((j & 1) == 0) {
+                if (j < 7) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, q + j + 1, x1);
+                mma_frags<DT, A>(tcur, x0, acc);
+            } else {
+                if (j < 7 || !last) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, q + j + 1, x0);
+                mma_frags<DT, A>(tcur, x1, acc);
+            }
+            load_tap<DT>(tap(s8 + 8 + j), lane, tcur);
+        }
+    }
+}
+
+// LINEAR layouts: raw window by direct loads, converted between chunks.
+//   chunk c computes from copies[c & 1] while raw(c+1) is in flight; then the
+//   work-group waits for it, converts it into copies[(c+1) & 1] and issues raw(c+2).
+template <int DT, int A, int LM>
+__device__ __forceinline__ void tile_loop_linear(const MfmaArgs& a, const ClipArg& c, const Geo& g, int64_t k0,
+                                                 int lo, int hi, const uint8_t* __restrict__ tbase, bool al16,
+                                                 float beta, uint8_t* lds, f32x16 (&acc)[A]) {
+    using T = Tr<DT>;
+    const int chunk = a.chunk_steps;   // multiple of 8
+    const int lane = threadIdx.x & 63;
+    const int swz = g.swz < 0 ? 31 : g.swz;
+    uint8_t* raw = lds + 2 * a.buf_bytes;
+    int base[A], unit0[A];
+    lane_bases<DT, A, LM>(c, g, base, unit0);
+    auto jb_of = [&](int ks_c) { return k0 * c.hop + (int64_t)T::KS * ks_c; };
+    auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
+
+    const int nchunks = (hi - lo + chunk) / chunk;
+    raw_issue<DT>(c, g, jb_of(lo), al16, raw);
+    Frag<DT> ta[4], tb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        load_tap<DT>(tap(lo + j), lane, ta[j]);
+        load_tap<DT>(tap(lo + 4 + j), lane, tb[j]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    raw_convert<DT>(c, g, jb_of(lo), al16, beta, raw, lds, 0);
+    __syncthreads();
+    if (nchunks > 1) raw_issue<DT>(c, g, jb_of(lo + chunk), al16, raw);
+
+    for (int ci = 0; ci < nchunks; ++ci) {
+        const int ks_c = lo + ci * chunk;
+        const int ns = min(chunk, hi - ks_c + 1);   // multiple of 8
+        compute_chunk<DT, A, LM>(lds + (ci & 1) * a.buf_bytes, g, swz, base, unit0, ks_c, ns, hi, lo, tbase,
+                                 ta, tb, acc);
+        if (ci + 1 < nchunks) {
+            __builtin_amdgcn_s_waitcnt(0);             // raw(ci+1) has landed in LDS
+            __syncthreads();
+            raw_convert<DT>(c, g, jb_of(ks_c + chunk), al16, beta, raw, lds, ((ci + 1) & 1) * a.buf_bytes);
+            __syncthreads();
+            if (ci + 2 < nchunks) raw_issue<DT>(c, g, jb_of(ks_c + 2 * chunk), al16, raw);
+        }
+    }
+}
+
+// ROWS layout: register-prefetched staging, one barrier per chunk.
+template <int DT, int A>
+__device__ __forceinline__ void tile_loop_rows(const MfmaArgs& a, const ClipArg& c, const Geo& g, int F, int64_t k0,
+                                               int lo, int hi, const uint8_t* __restrict__ tbase, bool al16,
+                                               float beta, uint8_t* lds, f32x16 (&acc)[A]) {
+    using T = Tr<DT>;
+    const int chunk = a.chunk_steps;   // multiple of 8
+    const int lane = threadIdx.x & 63;
+    int base[A], unit0[A];
+    lane_bases<DT, A, LM_ROWS>(c, g, base, unit0);
     auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
 
     const int nchunks = (hi - lo + chunk) / chunk;
     float r[stage_floats<DT>()];
     stage_load<DT>(c, g, F, chunk, k0, lo, al16, r);
     stage_store<DT>(c, g, F, chunk, k0, lo, al16, beta, r, lds, 0);
-    Frag<DT> t0, t1, t2, t3, x0[A], x1[A];
-    load_tap<DT>(tap(lo), lane, t0);
-    load_tap<DT>(tap(lo + 1), lane, t1);
-    load_tap<DT>(tap(lo + 2), lane, t2);
+    Frag<DT> ta[4], tb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        load_tap<DT>(tap(lo + j), lane, ta[j]);
+        load_tap<DT>(tap(lo + 4 + j), lane, tb[j]);
+    }
     __syncthreads();
-
     for (int ci = 0; ci < nchunks; ++ci) {
         const int ks_c = lo + ci * chunk;
         const int ns = min(chunk, hi - ks_c + 1);
-        const int buf = (ci & 1) * a.buf_bytes;
         const bool more = ci + 1 < nchunks;
         if (more) stage_load<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, r);
-        load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, 0, x0);
-        // ns is a multiple of 4: block ranges are padded to whole groups of four steps.
-        for (int q = 0; q < ns; q += 4) {
-            const int s = ks_c + q;
-            const bool last = q + 4 >= ns;        // the next chunk's buffer is not ready yet
-            load_tap<DT>(tap(s + 3), lane, t3);
-            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 1, x1);
-            mma_frags<DT, A>(t0, x0, acc);
-            load_tap<DT>(tap(s + 4), lane, t0);
-            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 2, x0);
-            mma_frags<DT, A>(t1, x1, acc);
-            load_tap<DT>(tap(s + 5), lane, t1);
-            load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 3, x1);
-            mma_frags<DT, A>(t2, x0, acc);
-            load_tap<DT>(tap(s + 6), lane, t2);
-            if (!last) load_x<DT, A, MODE>(lds, buf, g.plane_bytes, swz, base, unit0, q + 4, x0);
-            mma_frags<DT, A>(t3, x1, acc);
-        }
+        compute_chunk<DT, A, LM_ROWS>(lds + (ci & 1) * a.buf_bytes, g, 31, base, unit0, ks_c, ns, hi, lo, tbase,
+                                      ta, tb, acc);
         if (more) stage_store<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, beta, r, lds, ((ci + 1) & 1) * a.buf_bytes);
         __syncthreads();
     }
@@ -505,7 +698,9 @@ __device__ __forceinline__ void tile_loop(const MfmaArgs& a, const ClipArg& c, c
 // One work-group tile: F = 128*A consecutive frames of one clip against one
 // 32-scale block.  Each wave owns A 32-frame blocks; every K-step is A MFMAs
 // sharing one tap fragment.
-template <int DT, int A>
+// PATHS: 0 both staging layouts, 1 LINEAR only, 2 ROWS only (a kernel that
+// carries only one layout needs fewer registers).
+template <int DT, int A, int PATHS>
 __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c, int tile, int blk,
                                              uint8_t* lds, float* red) {
     const int F = 32 * A * kMfmaWaves;
@@ -528,10 +723,14 @@ __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
 
-    if (g.mode == STAGE_LINEAR)
-        tile_loop<DT, A, STAGE_LINEAR>(a, c, g, F, k0, lo, hi, tbase, al16, beta, lds, acc);
-    else
-        tile_loop<DT, A, STAGE_ROWS>(a, c, g, F, k0, lo, hi, tbase, al16, beta, lds, acc);
+    if (PATHS != 1 && g.mode == STAGE_ROWS) {
+        if constexpr (PATHS != 1) tile_loop_rows<DT, A>(a, c, g, F, k0, lo, hi, tbase, al16, beta, lds, acc);
+    } else if constexpr (PATHS != 2) {
+        if (g.swz >= 0)
+            tile_loop_linear<DT, A, LM_LINEAR_SWZ>(a, c, g, k0, lo, hi, tbase, al16, beta, lds, acc);
+        else
+            tile_loop_linear<DT, A, LM_LINEAR>(a, c, g, k0, lo, hi, tbase, al16, beta, lds, acc);
+    }
 
     // Epilogue: optional descale (FP8), |.| unless signed output, coalesced store.
     const float inv_beta = 1.0f / beta;
@@ -560,14 +759,14 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-template <int DT, int A>
+template <int DT, int A, int PATHS>
 __global__ __launch_bounds__(256) void k_mfma_grid(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ float red[kMfmaWaves];
     int id = blockIdx.x;
     if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
     const int tile = id / a.ngroups, blk = id - tile * a.ngroups;
-    process_tile<DT, A>(a, a.clip, tile, blk, lds, red);
+    process_tile<DT, A, PATHS>(a, a.clip, tile, blk, lds, red);
 }
 
 template <int DT, int A>
@@ -589,7 +788,7 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
         const int local = t - a.tile_prefix[lo];
         const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
         const ClipArg c = a.clips[lo];
-        process_tile<DT, A>(a, c, tile, blk, lds, red);
+        process_tile<DT, A, 0>(a, c, tile, blk, lds, red);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -604,19 +803,24 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
 
 template <int DT, int A>
 static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
-    const size_t shm = 2 * (size_t)a.buf_bytes;
-    static bool attr_set[2] = {false, false};
-    if (shm > 64 * 1024 && !attr_set[persistent]) {
-        const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A>;
+    const size_t shm = 2 * (size_t)a.buf_bytes + (size_t)a.raw_bytes;
+    const int paths = persistent ? 0 : (a.clip.mode == STAGE_ROWS ? 2 : 1);
+    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A>
+                   : paths == 2 ? (const void*)k_mfma_grid<DT, A, 2> : (const void*)k_mfma_grid<DT, A, 1>;
+    static bool attr_set[3] = {false, false, false};
+    const int slot = persistent ? 0 : paths;
+    if (shm > 64 * 1024 && !attr_set[slot]) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            mfma_max_lds_bytes() - 1024);
         if (e != hipSuccess) return e;
-        attr_set[persistent] = true;
+        attr_set[slot] = true;
     }
     if (persistent)
         hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
+    else if (paths == 2)
+        hipLaunchKernelGGL((k_mfma_grid<DT, A, 2>), dim3(grid), dim3(256), shm, s, a);
     else
-        hipLaunchKernelGGL((k_mfma_grid<DT, A>), dim3(grid), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((k_mfma_grid<DT, A, 1>), dim3(grid), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
@@ -642,7 +846,7 @@ int mfma_max_lds_bytes() { return 160 * 1024; }
 template <int DT, int A>
 static int occ2(int persistent, size_t shm) {
     int n = 0;
-    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A>;
+    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A, 1>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, shm) != hipSuccess) return 1;
     return n;
 }
