@@ -107,6 +107,8 @@ hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, cons
 hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,
                        int grid, hipStream_t s);
 int mfma_max_lds_bytes();
+// Allow every MFMA kernel the full dynamic LDS; call once, outside graph capture.
+hipError_t mfma_init_attributes();
 // Resident work-groups per CU for a kernel instance with `shm` bytes of dynamic LDS.
 int mfma_occupancy(int dt, int A, int nb, int persistent, size_t shm);
 

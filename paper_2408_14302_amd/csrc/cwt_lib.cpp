@@ -139,10 +139,13 @@ static Staging staging_for(int dt, int hop, int F, int chunk) {
             lin_conflicts = true;
         }
     }
-    if (lin <= rows && !lin_conflicts) {
+    // Compare the whole LDS footprint: two operand buffers, plus the raw FP32
+    // window for the linear layout (raw_floats() in mfma.hip).
+    const int64_t raw = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;
+    if (2 * lin + raw <= 2 * rows && !lin_conflicts) {
         s.mode = STAGE_LINEAR;
         s.bytes = lin;
-        s.raw_bytes = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;   // raw_floats() in mfma.hip
+        s.raw_bytes = raw;
     } else {
         s.mode = STAGE_ROWS;
         s.bytes = rows;
@@ -552,17 +555,35 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
     const Bank& bk = *p0->bank;
 
-    // One configuration for the whole launch: the first plan's, moved on until
-    // every clip's staging buffer fits.  (FP32 has a single configuration.)
+    // One configuration and one chunk size for the whole launch: the first
+    // plan's configuration and the largest chunk for which the LDS of the
+    // worst clip (two operand buffers plus the raw window, each maximised over
+    // the clips) fits; other configurations are tried if none does.
     const bool fp32 = p0->dt == DT_FP32;
-    int cfg = p0->cfg;
+    int cfg = p0->cfg, chunk = 8;
     if (!fp32) {
-        for (int tries = 0; tries < kNumMfmaCfgs; ++tries) {
-            bool ok = true;
-            for (int i = 0; i < n && ok; ++i) ok = cfg_fits(plans[i], cfg, plans[i]->hop);
-            if (ok) break;
-            cfg = (cfg + 1) % kNumMfmaCfgs;
+        bool found = false;
+        for (int tries = 0; tries < kNumMfmaCfgs && !found; ++tries, cfg = (cfg + 1) % kNumMfmaCfgs) {
+            if (!cfg_fits(p0, cfg, p0->hop)) continue;
+            const int Fc = 128 * kMfmaCfgs[cfg].A;
+            int best = -1;
+            for (int ch = kMfmaCfgs[cfg].chunk; ch >= 8 && best < 0; ch -= 8) {
+                int64_t mb = 0, mr = 0;
+                for (int i = 0; i < n; ++i) {
+                    if (lens[i] == 0) continue;
+                    Staging st = staging_for(p0->dt, plans[i]->hop, Fc, ch);
+                    mb = std::max(mb, st.bytes);
+                    mr = std::max(mr, st.raw_bytes);
+                }
+                if (2 * mb + mr <= mfma_max_lds_bytes() - 2048) best = ch;
+            }
+            if (best > 0) {
+                chunk = best;
+                found = true;
+                break;
+            }
         }
+        if (!found) return fail(CWT_ERR_UNSUPPORTED, "no kernel configuration fits this batch's hops");
     }
     const MfmaCfg c = fp32 ? MfmaCfg{1, 1} : kMfmaCfgs[cfg];
     const int F = fp32 ? kDirectFrames : 128 * c.A;
@@ -580,9 +601,6 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     // Longest first (most tiles first) so the persistent grid drains evenly.
     std::vector<ClipArg> clips(n);
     int64_t maxbytes = 16;
-    int chunk = c.chunk;
-    if (!fp32)
-        for (int i : order) chunk = std::min(chunk, pick_chunk(p0->dt, plans[i]->hop, F, c.chunk));
     int64_t maxraw = 0;
     for (int i : order) {
         int64_t bytes = 0, raw = 0;
@@ -746,6 +764,12 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
         p->arch = di.arch;
         st = acquire_bank(p->dt, dev, sc, &p->bank);
         if (st != CWT_OK) return st;
+        {
+            static std::once_flag attr_once;   // kernel attributes, never during a graph capture
+            hipError_t ae = hipSuccess;
+            std::call_once(attr_once, [&] { ae = mfma_init_attributes(); });
+            if (ae != hipSuccess) return fail(CWT_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(ae));
+        }
         p->cfg = default_cfg(p->dt, hop);
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -804,24 +804,43 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
 template <int DT, int A>
 static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
     const size_t shm = 2 * (size_t)a.buf_bytes + (size_t)a.raw_bytes;
-    const int paths = persistent ? 0 : (a.clip.mode == STAGE_ROWS ? 2 : 1);
-    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A>
-                   : paths == 2 ? (const void*)k_mfma_grid<DT, A, 2> : (const void*)k_mfma_grid<DT, A, 1>;
-    static bool attr_set[3] = {false, false, false};
-    const int slot = persistent ? 0 : paths;
-    if (shm > 64 * 1024 && !attr_set[slot]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           mfma_max_lds_bytes() - 1024);
-        if (e != hipSuccess) return e;
-        attr_set[slot] = true;
-    }
+    if (shm > (size_t)mfma_max_lds_bytes() - 1024) return hipErrorInvalidValue;
+    (void)hipGetLastError();   // report only this launch's error
     if (persistent)
         hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
-    else if (paths == 2)
+    else if (a.clip.mode == STAGE_ROWS)
         hipLaunchKernelGGL((k_mfma_grid<DT, A, 2>), dim3(grid), dim3(256), shm, s, a);
     else
         hipLaunchKernelGGL((k_mfma_grid<DT, A, 1>), dim3(grid), dim3(256), shm, s, a);
     return hipGetLastError();
+}
+
+template <int DT, int A>
+static hipError_t attrs2() {
+    const int lds = mfma_max_lds_bytes() - 1024;
+    const void* fns[3] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A, 1>,
+                          (const void*)k_mfma_grid<DT, A, 2>};
+    for (const void* fn : fns) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int DT>
+static hipError_t attrs1() {
+    hipError_t e = attrs2<DT, 1>();
+    if (e == hipSuccess) e = attrs2<DT, 2>();
+    if (e == hipSuccess) e = attrs2<DT, 4>();
+    return e;
+}
+
+hipError_t mfma_init_attributes() {
+    hipError_t e = attrs1<DT_BF16>();
+    if (e == hipSuccess) e = attrs1<DT_FP16>();
+    if (e == hipSuccess) e = attrs1<DT_BF16X3>();
+    if (e == hipSuccess) e = attrs1<DT_FP8>();
+    return e;
 }
 
 template <int DT>
