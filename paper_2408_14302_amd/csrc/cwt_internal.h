@@ -80,6 +80,8 @@ struct MfmaArgs {
     int32_t buf_bytes;     // bytes of one LDS staging buffer (two are used)
     int32_t raw_bytes;     // bytes of the raw FP32 window buffer (linear staging)
     int32_t xcd_remap;     // 1: map consecutive tiles to the same XCD
+    int32_t split_wb;      // row-layout tiles: scale blocks per work-group (1, 2 or 4)
+    int32_t split_chunk;   // row-layout tiles: K-steps per chunk (a multiple of 8)
     // single clip (grid launch)
     ClipArg clip;
     // batch (persistent launch)

@@ -116,63 +116,78 @@ struct Staging {
     int64_t raw_bytes;  // LINEAR: the raw FP32 window buffer
 };
 
-static Staging staging_for(int dt, int hop, int F, int chunk) {
+static const int64_t kLdsBudget = 52 * 1024;   // three work-groups per CU
+
+// The LINEAR layout for F frames and `chunk` K-steps.
+static Staging linear_staging(int dt, int hop, int F, int chunk) {
     const int U = 16 / elem_bytes(dt), KS = kstep_of(dt), P = planes_of(dt);
     Staging s;
+    s.mode = STAGE_LINEAR;
     const int gh = (int)gcd64(hop, U);
     s.copies = U / gh;
-    int64_t pmax = (int64_t)(F - 1) * hop + (int64_t)KS * chunk - 1;
-    int64_t len_u = ((pmax / U + 1) + 15) & ~int64_t(15);
-    int64_t cs = len_u + (s.copies > 1 ? 16 / s.copies : 0);
-    int64_t lin = (int64_t)s.copies * cs * 16 * P;
-    int64_t rows = (int64_t)F * (KS * chunk / U + 1) * 16 * P;
-    bool pow2 = (hop & (hop - 1)) == 0;
-    int q = hop / U;
+    const int64_t pmax = (int64_t)(F - 1) * hop + (int64_t)KS * chunk - 1;
+    const int64_t len_u = ((pmax / U + 1) + 15) & ~int64_t(15);
+    const int64_t cs = len_u + (s.copies > 1 ? 16 / s.copies : 0);
+    s.bytes = (int64_t)s.copies * cs * 16 * P;
+    s.raw_bytes = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;   // raw_floats() in mfma.hip
     s.swz = -1;
-    bool lin_conflicts = false;
-    if (s.copies == 1 && hop % U == 0 && q % 2 == 0) {
-        if (pow2) {
-            int sh = 0;
-            while ((1 << sh) < q) ++sh;
-            s.swz = sh;
-        } else {
-            lin_conflicts = true;
-        }
-    }
-    // Compare the whole LDS footprint: two operand buffers, plus the raw FP32
-    // window for the linear layout (raw_floats() in mfma.hip).
-    const int64_t raw = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;
-    if (2 * lin + raw <= 2 * rows && !lin_conflicts) {
-        s.mode = STAGE_LINEAR;
-        s.bytes = lin;
-        s.raw_bytes = raw;
-    } else {
-        s.mode = STAGE_ROWS;
-        s.bytes = rows;
-        s.swz = -1;
-        s.raw_bytes = 0;
+    const int64_t q = hop / U;
+    if (s.copies == 1 && hop % U == 0 && q % 2 == 0 && (hop & (hop - 1)) == 0) {
+        int sh = 0;
+        while ((int64_t(1) << sh) < q) ++sh;
+        s.swz = sh;                            // XOR swizzle for power-of-two hops
     }
     return s;
 }
 
-// Largest chunk (multiple of 8, <= chunk_max) whose LDS (two operand buffers
-// plus the raw window) fits kLdsBudget and, for the row layout, whose units fit
-// the kernel's register prefetch (32 floats per thread, 256 threads); 8 if none
-// does (the kernel then stages the overflow directly).
-static const int64_t kLdsBudget = 52 * 1024;   // three work-groups per CU
+// The row layout of SPLIT tiles (F frames, `chunk` K-steps).
+static Staging split_staging(int dt, int F, int chunk) {
+    const int U = 16 / elem_bytes(dt), KS = kstep_of(dt), P = planes_of(dt);
+    Staging s;
+    s.mode = STAGE_ROWS;
+    s.copies = 1;
+    s.swz = -1;
+    s.bytes = (int64_t)F * (KS * chunk / U + 1) * 16 * P;
+    s.raw_bytes = 0;
+    return s;
+}
+
+// A clip uses the LINEAR layout (128*A-frame tiles, one scale block each) when
+// that layout fits kLdsBudget at the smallest chunk; otherwise SPLIT tiles.
+// The choice depends only on (dtype, hop, A), so a clip is laid out the same
+// way alone and in any batch.
+static bool use_linear(int dt, int hop, int F) {
+    Staging s = linear_staging(dt, hop, F, 8);
+    return 2 * s.bytes + s.raw_bytes <= kLdsBudget;
+}
+
+// Largest LINEAR chunk (multiple of 8, <= chunk_max) within kLdsBudget.
 static int pick_chunk(int dt, int hop, int F, int chunk_max) {
-    const int U = 16 / elem_bytes(dt), KS = kstep_of(dt);
     for (int chunk = chunk_max; chunk >= 8; chunk -= 8) {
-        Staging s = staging_for(dt, hop, F, chunk);
-        const int64_t lds = 2 * s.bytes + s.raw_bytes;
-        if (s.mode == STAGE_LINEAR) {
-            if (lds <= kLdsBudget) return chunk;       // the conversion pass has no register limit
-        } else {
-            const int64_t units = (int64_t)F * (KS * chunk / U), cap = 256 * (32 / U);
-            if (units <= cap && lds <= kLdsBudget) return chunk;
-        }
+        Staging s = linear_staging(dt, hop, F, chunk);
+        if (2 * s.bytes + s.raw_bytes <= kLdsBudget) return chunk;
     }
     return 8;
+}
+
+// SPLIT geometry of a bank with `nblocks` 32-scale blocks: blocks per
+// work-group (1, 2 or 4), frames per tile, and the largest chunk (<= 32) whose
+// two row buffers take at most 40 KiB.
+struct SplitGeo {
+    int wb, F, chunk, groups;
+};
+static SplitGeo split_geo(int dt, int nblocks) {
+    SplitGeo g;
+    g.wb = nblocks >= 3 ? 4 : (nblocks == 2 ? 2 : 1);
+    g.F = 32 * (4 / g.wb);
+    g.groups = (nblocks + g.wb - 1) / g.wb;
+    g.chunk = 8;
+    for (int ch = 32; ch >= 8; ch -= 8)
+        if (2 * split_staging(dt, g.F, ch).bytes <= 40 * 1024) {
+            g.chunk = ch;
+            break;
+        }
+    return g;
 }
 
 // ---------------------------------------------------------------------------
@@ -280,11 +295,13 @@ static cwt_status build_bank(int dt, int device, const std::vector<double>& scal
                 if (p < S) Mb = std::max(Mb, bk->M_sorted[p]);
             }
             // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb]
-            B.lo = (int)std::floor(-(double)Mb / KS);
-            B.hi = Mb / KS;
-            // whole groups of eight steps (the extra steps hold zero taps), so the
-            // kernel's eight-step K loop never ends inside a group
-            B.hi = B.lo + ((B.hi - B.lo + 1 + 7) / 8) * 8 - 1;
+            // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb], widened to whole
+            // groups of eight steps aligned to multiples of 8 (the extra steps
+            // hold zero taps): the K loop then never ends inside a group, and
+            // any 8-aligned chunk meets every block on group boundaries
+            const int lo0 = (int)std::floor(-(double)Mb / KS), hi0 = Mb / KS;
+            B.lo = (int)std::floor(lo0 / 8.0) * 8;
+            B.hi = (int)std::ceil((hi0 + 1) / 8.0) * 8 - 1;
             B.frag_off = off;
             off += (int64_t)(B.hi - B.lo + 1) * step_bytes;
             bk->blocks.push_back(B);
@@ -384,26 +401,34 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
     std::rename(tmp.c_str(), path);
 }
 
+// Default configuration: the widest tile (A = 4, 2, 1) whose LINEAR layout fits
+// the LDS budget; FP8 always uses A = 1.  Large hops fall through to A = 1 and
+// SPLIT tiles.
 static int default_cfg(int dt, int hop) {
-    if (dt == DT_FP32 || dt == DT_FP8) return 0;
-    return hop <= 8 ? 2 : (hop <= 64 ? 1 : 0);   // A = 4 / 2 / 1 as the hop grows
+    if (dt == DT_FP32 || dt == DT_FP8) return 0;      // {1, 64}
+    if (use_linear(dt, hop, 512)) return 2;          // {4, 32}
+    if (use_linear(dt, hop, 256)) return 1;          // {2, 64}
+    return 0;                                         // {1, 64}
 }
 
 static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     if (p->dt == DT_FP32) return cfg == 0;
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
     const MfmaCfg& c = kMfmaCfgs[cfg];
-    // FP8 scales the signal per 128-frame tile; a fixed tile keeps every clip's
-    // result independent of the configuration and of the batch it runs in.
+    // FP8 scales the signal per tile; a fixed tile keeps every clip's result
+    // independent of the configuration and of the batch it runs in.
     if (p->dt == DT_FP8 && c.A != 1) return false;
-    Staging s = staging_for(p->dt, hop, 128 * c.A, pick_chunk(p->dt, hop, 128 * c.A, c.chunk));
-    return 2 * s.bytes + s.raw_bytes <= mfma_max_lds_bytes() - 2048;
+    (void)hop;
+    return true;   // a layout always exists: LINEAR within budget, or SPLIT tiles
 }
 
 // ---------------------------------------------------------------------------
 // Launch of one clip.
-static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int F,
-                         int chunk, int64_t* bytes_out, int64_t* raw_out = nullptr) {
+// One clip's kernel record.  MFMA: LINEAR tiles of F = 128*A frames (chunk
+// `chunk`) or SPLIT tiles; *bytes_out/*raw_out receive its LDS needs and
+// *tiles_out its work-group tiles (frame tiles x block groups).
+static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int A, int chunk,
+                         int64_t* bytes_out, int64_t* raw_out, int64_t* tiles_out) {
     ClipArg c;
     std::memset(&c, 0, sizeof(c));
     c.x = x;
@@ -411,21 +436,38 @@ static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float
     c.len = len;
     c.hop = p->hop;
     c.K = (len + p->hop - 1) / p->hop;
-    c.ntile = (int32_t)((c.K + F - 1) / F);
-    if (p->dt != DT_FP32) {
-        Staging s = staging_for(p->dt, p->hop, F, chunk);
-        c.mode = s.mode;
-        c.copies = s.copies;
-        c.swz = s.swz;
-        if (bytes_out) *bytes_out = s.bytes;
-        if (raw_out) *raw_out = s.raw_bytes;
+    if (p->dt == DT_FP32) {
+        c.ntile = (int32_t)((c.K + kDirectFrames - 1) / kDirectFrames);
+        if (tiles_out) *tiles_out = (int64_t)c.ntile * (((int64_t)p->bank->dgroups.size() + kDirectWaves - 1) / kDirectWaves);
+        return c;
     }
+    const int nblk = (int)p->bank->blocks.size();
+    const int F = 128 * A;
+    Staging s;
+    int64_t tiles;
+    if (use_linear(p->dt, p->hop, F)) {
+        s = linear_staging(p->dt, p->hop, F, chunk);
+        c.ntile = (int32_t)((c.K + F - 1) / F);
+        tiles = (int64_t)c.ntile * nblk;
+    } else {
+        SplitGeo sg = split_geo(p->dt, nblk);
+        s = split_staging(p->dt, sg.F, sg.chunk);
+        c.ntile = (int32_t)((c.K + sg.F - 1) / sg.F);
+        tiles = (int64_t)c.ntile * sg.groups;
+    }
+    c.mode = s.mode;
+    c.copies = s.copies;
+    c.swz = s.swz;
+    if (bytes_out) *bytes_out = s.bytes;
+    if (raw_out) *raw_out = s.raw_bytes;
+    if (tiles_out) *tiles_out = tiles;
     return c;
 }
 
 static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64_t len, float* out,
                              hipStream_t stream) {
     const Bank& bk = *p->bank;
+    int64_t tiles = 0;
     if (p->dt == DT_FP32) {
         DirectArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -433,30 +475,32 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
         a.groups = bk.d_dgroups;
         a.ngroups = (int)bk.dgroups.size();
         a.signed_out = p->signed_out;
-        a.clip = make_clip(p, x, len, out, kDirectFrames, 1, nullptr);
+        a.clip = make_clip(p, x, len, out, 1, 8, nullptr, nullptr, &tiles);
         a.xcd_remap = 1;
         HIP_TRY(launch_direct(a, stream), "direct launch");
         return CWT_OK;
     }
     const MfmaCfg& c = kMfmaCfgs[cfg];
     const int F = 128 * c.A;
+    const int chunk = pick_chunk(p->dt, p->hop, F, c.chunk);
+    const SplitGeo sg = split_geo(p->dt, (int)bk.blocks.size());
     MfmaArgs a;
     std::memset(&a, 0, sizeof(a));
     a.frags = bk.d_frags;
     a.blocks = bk.d_blocks;
     a.ngroups = (int)bk.blocks.size();
     a.signed_out = p->signed_out;
-    const int chunk = pick_chunk(p->dt, p->hop, F, c.chunk);
     a.chunk_steps = chunk;
     a.frames = F;
+    a.split_wb = sg.wb;
+    a.split_chunk = sg.chunk;
     int64_t bytes = 0, raw = 0;
-    a.clip = make_clip(p, x, len, out, F, chunk, &bytes, &raw);
+    a.clip = make_clip(p, x, len, out, c.A, chunk, &bytes, &raw, &tiles);
     a.buf_bytes = (int32_t)bytes;
     a.raw_bytes = (int32_t)raw;
     a.xcd_remap = 1;
-    int64_t grid = (int64_t)a.clip.ntile * a.ngroups;
-    if (grid > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
-    HIP_TRY(launch_mfma(p->dt, c.A, 1, a, 0, (int)grid, stream), "mfma launch");
+    if (tiles > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
+    HIP_TRY(launch_mfma(p->dt, c.A, 1, a, 0, (int)tiles, stream), "mfma launch");
     return CWT_OK;
 }
 
@@ -555,40 +599,30 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
     const Bank& bk = *p0->bank;
 
-    // One configuration and one chunk size for the whole launch: the first
-    // plan's configuration and the largest chunk for which the LDS of the
-    // worst clip (two operand buffers plus the raw window, each maximised over
-    // the clips) fits; other configurations are tried if none does.
+    // One configuration for the whole launch (the first plan's) and one LINEAR
+    // chunk: the largest for which the worst clip's LDS (operand buffers plus
+    // raw window, maximised over the clips) fits the budget.  SPLIT clips have
+    // a fixed geometry per bank.
     const bool fp32 = p0->dt == DT_FP32;
-    int cfg = p0->cfg, chunk = 8;
+    const int cfg = p0->cfg;
+    const MfmaCfg c = fp32 ? MfmaCfg{1, 8} : kMfmaCfgs[cfg];
+    int chunk = 8;
     if (!fp32) {
-        bool found = false;
-        for (int tries = 0; tries < kNumMfmaCfgs && !found; ++tries, cfg = (cfg + 1) % kNumMfmaCfgs) {
-            if (!cfg_fits(p0, cfg, p0->hop)) continue;
-            const int Fc = 128 * kMfmaCfgs[cfg].A;
-            int best = -1;
-            for (int ch = kMfmaCfgs[cfg].chunk; ch >= 8 && best < 0; ch -= 8) {
-                int64_t mb = 0, mr = 0;
-                for (int i = 0; i < n; ++i) {
-                    if (lens[i] == 0) continue;
-                    Staging st = staging_for(p0->dt, plans[i]->hop, Fc, ch);
-                    mb = std::max(mb, st.bytes);
-                    mr = std::max(mr, st.raw_bytes);
-                }
-                if (2 * mb + mr <= mfma_max_lds_bytes() - 2048) best = ch;
+        for (int ch = c.chunk; ch >= 8; ch -= 8) {
+            int64_t mb = 0, mr = 0;
+            for (int i = 0; i < n; ++i) {
+                if (lens[i] == 0 || !use_linear(p0->dt, plans[i]->hop, 128 * c.A)) continue;
+                Staging st = linear_staging(p0->dt, plans[i]->hop, 128 * c.A, ch);
+                mb = std::max(mb, st.bytes);
+                mr = std::max(mr, st.raw_bytes);
             }
-            if (best > 0) {
-                chunk = best;
-                found = true;
+            if (2 * mb + mr <= kLdsBudget) {
+                chunk = ch;
                 break;
             }
         }
-        if (!found) return fail(CWT_ERR_UNSUPPORTED, "no kernel configuration fits this batch's hops");
     }
-    const MfmaCfg c = fp32 ? MfmaCfg{1, 1} : kMfmaCfgs[cfg];
-    const int F = fp32 ? kDirectFrames : 128 * c.A;
-    const int64_t groups_per_tile = fp32 ? ((int64_t)bk.dgroups.size() + kDirectWaves - 1) / kDirectWaves
-                                         : (int64_t)bk.blocks.size();
+    const SplitGeo sg = fp32 ? SplitGeo{1, 32, 8, 1} : split_geo(p0->dt, (int)bk.blocks.size());
 
     // Wait until the pinned buffer we are about to overwrite has been consumed.
     const int slot = b->flip;
@@ -600,15 +634,16 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         if (lens[i] > 0) order.push_back(i);
     // Longest first (most tiles first) so the persistent grid drains evenly.
     std::vector<ClipArg> clips(n);
+    std::vector<int64_t> ctiles(n, 0);
     int64_t maxbytes = 16;
     int64_t maxraw = 0;
     for (int i : order) {
         int64_t bytes = 0, raw = 0;
-        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], F, chunk, &bytes, &raw);
+        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], c.A, chunk, &bytes, &raw, &ctiles[i]);
         maxbytes = std::max(maxbytes, bytes);
         maxraw = std::max(maxraw, raw);
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return clips[a].ntile > clips[bq].ntile; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return ctiles[a] > ctiles[bq]; });
     const int nc = (int)order.size();
     if (nc == 0) return CWT_OK;
     ClipArg* hc = (ClipArg*)(host + 16);
@@ -617,7 +652,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     for (int j = 0; j < nc; ++j) {
         hc[j] = clips[order[j]];
         hp[j] = (int32_t)total;
-        total += (int64_t)clips[order[j]].ntile * groups_per_tile;
+        total += ctiles[order[j]];
         if (total > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "batch has too many tiles");
     }
     hp[nc] = (int32_t)total;
@@ -648,7 +683,9 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.ngroups = (int)bk.blocks.size();
     a.signed_out = p0->signed_out;
     a.chunk_steps = chunk;
-    a.frames = F;
+    a.frames = 128 * c.A;
+    a.split_wb = sg.wb;
+    a.split_chunk = sg.chunk;
     a.buf_bytes = (int32_t)maxbytes;
     a.raw_bytes = (int32_t)maxraw;
     a.xcd_remap = 0;

@@ -1,7 +1,7 @@
 // Strided-frame contraction on the matrix cores (gfx950 MFMA).
 //
-// For one work-group tile (F consecutive frames k0 .. k0+F-1 of one clip, and
-// one group of up to four 32-scale blocks) it computes
+// For one work-group tile (consecutive frames k0 .. k0+F-1 of one clip and one
+// or more 32-scale blocks) it computes
 //     W[i][k] = sum_m t_i[m] * x~[k*hop + m]          (Eq. (1), Sec. II-A/II-B)
 // as C[32 scales x 32 frames] += T[32 x KS] * X[KS x 32] per MFMA, where
 //     T[r][kk] = t_r[KS*ks + kk]                (bank fragment, L2 resident)
@@ -19,8 +19,8 @@
 //           power-of-two hops an XOR swizzle of the 16-byte unit index spreads
 //           the frame-strided reads over the LDS banks.
 //   ROWS    one padded row per frame holding x~[(k0+f)*hop + KS*ks_c + c]; used
-//           when the frames are so far apart that the linear window would be
-//           larger.
+//           (with small tiles whose waves take different scale blocks) when the
+//           frames are so far apart that the linear window would not fit.
 // Summation order per coefficient: K-steps ascending, fixed per block, so the
 // result does not depend on the tile, the launch shape or the batch.
 #include "cwt_internal.h"
@@ -586,27 +586,32 @@ __device__ __forceinline__ void lane_bases(const ClipArg& c, const Geo& g, int (
 // Tap fragments (from L2) are loaded eight steps ahead into two banks of four
 // register sets, signal fragments (from LDS) one step ahead into a ring of two;
 // every slot is a compile-time constant.
+// The MFMAs of steps ks_c+d0 .. ks_c+d0+ns-1 (ns a multiple of 8) of the chunk
+// starting at ks_c, from LDS buffer `cur`.  Tap fragments (from L2) are loaded
+// eight steps ahead into two banks of four register sets, signal fragments
+// (from LDS) one step ahead into a ring of two; every slot is a compile-time
+// constant.
 template <int DT, int A, int LM>
 __device__ __forceinline__ void compute_chunk(const uint8_t* cur, const Geo& g, int swz, const int (&base)[A],
-                                              const int (&unit0)[A], int ks_c, int ns, int hi, int lo,
+                                              const int (&unit0)[A], int ks_c, int d0, int ns, int hi, int lo,
                                               const uint8_t* __restrict__ tbase, Frag<DT> (&ta)[4],
                                               Frag<DT> (&tb)[4], f32x16 (&acc)[A]) {
     using T = Tr<DT>;
     const int lane = threadIdx.x & 63;
     auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
     Frag<DT> x0[A], x1[A];
-    load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, 0, x0);
+    load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0, x0);
     for (int q = 0; q < ns; q += 8) {
-        const int s8 = ks_c + q;
+        const int s8 = ks_c + d0 + q;
         const bool last = q + 8 >= ns;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             Frag<DT>& tcur = j < 4 ? ta[j & 3] : tb[j & 3];
             if ((j & 1) == 0) {
-                if (j < 7) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, q + j + 1, x1);
+                if (j < 7) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0 + q + j + 1, x1);
                 mma_frags<DT, A>(tcur, x0, acc);
             } else {
-                if (j < 7 || !last) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, q + j + 1, x0);
+                if (j < 7 || !last) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0 + q + j + 1, x0);
                 mma_frags<DT, A>(tcur, x1, acc);
             }
             load_tap<DT>(tap(s8 + 8 + j), lane, tcur);
@@ -648,7 +653,7 @@ __device__ __forceinline__ void tile_loop_linear(const MfmaArgs& a, const ClipAr
     for (int ci = 0; ci < nchunks; ++ci) {
         const int ks_c = lo + ci * chunk;
         const int ns = min(chunk, hi - ks_c + 1);   // multiple of 8
-        compute_chunk<DT, A, LM>(lds + (ci & 1) * a.buf_bytes, g, swz, base, unit0, ks_c, ns, hi, lo, tbase,
+        compute_chunk<DT, A, LM>(lds + (ci & 1) * a.buf_bytes, g, swz, base, unit0, ks_c, 0, ns, hi, lo, tbase,
                                  ta, tb, acc);
         if (ci + 1 < nchunks) {
             __builtin_amdgcn_s_waitcnt(0);             // raw(ci+1) has landed in LDS
@@ -660,47 +665,90 @@ __device__ __forceinline__ void tile_loop_linear(const MfmaArgs& a, const ClipAr
     }
 }
 
-// ROWS layout: register-prefetched staging, one barrier per chunk.
-template <int DT, int A>
-__device__ __forceinline__ void tile_loop_rows(const MfmaArgs& a, const ClipArg& c, const Geo& g, int F, int64_t k0,
-                                               int lo, int hi, const uint8_t* __restrict__ tbase, bool al16,
-                                               float beta, uint8_t* lds, f32x16 (&acc)[A]) {
+// SPLIT tile (row layout): F = 32*WF consecutive frames against up to WB =
+// 4/WF consecutive 32-scale blocks; wave w takes frame block w / WB and block
+// slot (w + tile) % WB (rotated so that the widest block of a group does not
+// always land on the same SIMD).  All waves share the staged rows; each wave
+// runs only the K-steps of its own block.
+template <int DT>
+__device__ __forceinline__ void process_tile_split(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
+                                                   uint8_t* lds, float* red) {
     using T = Tr<DT>;
-    const int chunk = a.chunk_steps;   // multiple of 8
-    const int lane = threadIdx.x & 63;
-    int base[A], unit0[A];
-    lane_bases<DT, A, LM_ROWS>(c, g, base, unit0);
+    const int WB = a.split_wb, WF = kMfmaWaves / WB, F = 32 * WF;
+    const int chunk = a.split_chunk;   // multiple of 8
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 31, hg = lane >> 5;
+    const int wf = w / WB, wb = w - wf * WB;
+    const int64_t k0 = (int64_t)tile * F;
+    const int b0 = grp * WB, nb = min(WB, a.ngroups - b0);
+    int glo = a.blocks[b0].lo, ghi = a.blocks[b0].hi;
+    for (int i = 1; i < nb; ++i) {
+        glo = min(glo, a.blocks[b0 + i].lo);
+        ghi = max(ghi, a.blocks[b0 + i].hi);
+    }
+    const int slot = (wb + tile) % WB;
+    const bool has = slot < nb;
+    const MfmaBlock* __restrict__ B = a.blocks + b0 + (has ? slot : 0);
+    const int lo = B->lo, hi = B->hi;
+    const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
+    const Geo g = make_geo<DT>(c, F, chunk);
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
+    float beta = 1.0f;
+    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
+
+    f32x16 acc[1];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[0][v] = 0.0f;
+    const int base[1] = {((32 * wf + n) * g.rs + hg * T::LU) * 16};
+    const int unit0[1] = {0};
     auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
 
-    const int nchunks = (hi - lo + chunk) / chunk;
+    const int nchunks = (ghi - glo + chunk) / chunk;
     float r[stage_floats<DT>()];
-    stage_load<DT>(c, g, F, chunk, k0, lo, al16, r);
-    stage_store<DT>(c, g, F, chunk, k0, lo, al16, beta, r, lds, 0);
+    stage_load<DT>(c, g, F, chunk, k0, glo, al16, r);
+    stage_store<DT>(c, g, F, chunk, k0, glo, al16, beta, r, lds, 0);
     Frag<DT> ta[4], tb[4];
+    if (has) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        load_tap<DT>(tap(lo + j), lane, ta[j]);
-        load_tap<DT>(tap(lo + 4 + j), lane, tb[j]);
+        for (int j = 0; j < 4; ++j) {
+            load_tap<DT>(tap(lo + j), lane, ta[j]);
+            load_tap<DT>(tap(lo + 4 + j), lane, tb[j]);
+        }
     }
     __syncthreads();
     for (int ci = 0; ci < nchunks; ++ci) {
-        const int ks_c = lo + ci * chunk;
-        const int ns = min(chunk, hi - ks_c + 1);
+        const int ks_c = glo + ci * chunk;
+        const int ks_e = min(ks_c + chunk - 1, ghi);
         const bool more = ci + 1 < nchunks;
         if (more) stage_load<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, r);
-        compute_chunk<DT, A, LM_ROWS>(lds + (ci & 1) * a.buf_bytes, g, 31, base, unit0, ks_c, ns, hi, lo, tbase,
-                                      ta, tb, acc);
+        const int s0 = max(ks_c, lo), s1 = min(ks_e, hi);   // block ranges are 8-aligned
+        if (has && s0 <= s1)
+            compute_chunk<DT, 1, LM_ROWS>(lds + (ci & 1) * a.buf_bytes, g, 31, base, unit0, ks_c, s0 - ks_c,
+                                          s1 - s0 + 1, hi, lo, tbase, ta, tb, acc);
         if (more) stage_store<DT>(c, g, F, chunk, k0, ks_c + chunk, al16, beta, r, lds, ((ci + 1) & 1) * a.buf_bytes);
         __syncthreads();
     }
+    if (!has) return;
+    const float inv_beta = 1.0f / beta;
+    const int64_t k = k0 + 32 * wf + n;
+    if (k >= c.K) return;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
+        const int row = B->rows[rr];
+        if (row < 0) continue;
+        float val = acc[0][v];
+        if constexpr (DT == DT_FP8) val = val * (B->inv_alpha[rr] * inv_beta);
+        if (!a.signed_out) val = fabsf(val);
+        __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
+    }
 }
 
-// One work-group tile: F = 128*A consecutive frames of one clip against one
+// LINEAR work-group tile: F = 128*A consecutive frames of one clip against one
 // 32-scale block.  Each wave owns A 32-frame blocks; every K-step is A MFMAs
 // sharing one tap fragment.
-// PATHS: 0 both staging layouts, 1 LINEAR only, 2 ROWS only (a kernel that
-// carries only one layout needs fewer registers).
-template <int DT, int A, int PATHS>
+// LINEAR tile.
+template <int DT, int A>
 __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c, int tile, int blk,
                                              uint8_t* lds, float* red) {
     const int F = 32 * A * kMfmaWaves;
@@ -723,14 +771,10 @@ __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
 
-    if (PATHS != 1 && g.mode == STAGE_ROWS) {
-        if constexpr (PATHS != 1) tile_loop_rows<DT, A>(a, c, g, F, k0, lo, hi, tbase, al16, beta, lds, acc);
-    } else if constexpr (PATHS != 2) {
-        if (g.swz >= 0)
-            tile_loop_linear<DT, A, LM_LINEAR_SWZ>(a, c, g, k0, lo, hi, tbase, al16, beta, lds, acc);
-        else
-            tile_loop_linear<DT, A, LM_LINEAR>(a, c, g, k0, lo, hi, tbase, al16, beta, lds, acc);
-    }
+    if (g.swz >= 0)
+        tile_loop_linear<DT, A, LM_LINEAR_SWZ>(a, c, g, k0, lo, hi, tbase, al16, beta, lds, acc);
+    else
+        tile_loop_linear<DT, A, LM_LINEAR>(a, c, g, k0, lo, hi, tbase, al16, beta, lds, acc);
 
     // Epilogue: optional descale (FP8), |.| unless signed output, coalesced store.
     const float inv_beta = 1.0f / beta;
@@ -759,14 +803,25 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-template <int DT, int A, int PATHS>
+template <int DT, int A>
 __global__ __launch_bounds__(256) void k_mfma_grid(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ float red[kMfmaWaves];
     int id = blockIdx.x;
     if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
     const int tile = id / a.ngroups, blk = id - tile * a.ngroups;
-    process_tile<DT, A, PATHS>(a, a.clip, tile, blk, lds, red);
+    process_tile<DT, A>(a, a.clip, tile, blk, lds, red);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_mfma_split(MfmaArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ float red[kMfmaWaves];
+    int id = blockIdx.x;
+    if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
+    const int ng = (a.ngroups + a.split_wb - 1) / a.split_wb;
+    const int tile = id / ng, grp = id - tile * ng;
+    process_tile_split<DT>(a, a.clip, tile, grp, lds, red);
 }
 
 template <int DT, int A>
@@ -786,9 +841,15 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
             if (a.tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const int local = t - a.tile_prefix[lo];
-        const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
         const ClipArg c = a.clips[lo];
-        process_tile<DT, A, 0>(a, c, tile, blk, lds, red);
+        if (c.mode == STAGE_LINEAR) {
+            const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
+            process_tile<DT, A>(a, c, tile, blk, lds, red);
+        } else {
+            const int ng = (a.ngroups + a.split_wb - 1) / a.split_wb;
+            const int tile = local / ng, grp = local - tile * ng;
+            process_tile_split<DT>(a, c, tile, grp, lds, red);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -809,17 +870,17 @@ static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream
     if (persistent)
         hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
     else if (a.clip.mode == STAGE_ROWS)
-        hipLaunchKernelGGL((k_mfma_grid<DT, A, 2>), dim3(grid), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((k_mfma_split<DT>), dim3(grid), dim3(256), shm, s, a);
     else
-        hipLaunchKernelGGL((k_mfma_grid<DT, A, 1>), dim3(grid), dim3(256), shm, s, a);
+        hipLaunchKernelGGL((k_mfma_grid<DT, A>), dim3(grid), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
 template <int DT, int A>
 static hipError_t attrs2() {
     const int lds = mfma_max_lds_bytes() - 1024;
-    const void* fns[3] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A, 1>,
-                          (const void*)k_mfma_grid<DT, A, 2>};
+    const void* fns[3] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A>,
+                          (const void*)k_mfma_split<DT>};
     for (const void* fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -865,7 +926,7 @@ int mfma_max_lds_bytes() { return 160 * 1024; }
 template <int DT, int A>
 static int occ2(int persistent, size_t shm) {
     int n = 0;
-    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A, 1>;
+    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, shm) != hipSuccess) return 1;
     return n;
 }
