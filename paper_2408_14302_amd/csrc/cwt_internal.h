@@ -64,11 +64,13 @@ struct ClipArg {
     int32_t ntile;   // frame tiles of this clip
     int32_t mode;    // staging mode for the MFMA kernel (see StageMode)
     int32_t copies;  // shifted copies (linear mode)
-    int32_t swz;     // XOR-swizzle shift (linear mode), -1 for none
-    int32_t pad;
+    int32_t swz;     // XOR-swizzle shift (linear and window modes), -1 for none
+    int32_t wb;      // window mode: 32-scale blocks per work-group (1, 2 or 4)
 };
 
-enum StageMode : int { STAGE_LINEAR = 0, STAGE_ROWS = 1 };
+// LINEAR: chunked linear window, one block per tile; ROWS: chunked per-frame
+// rows (SPLIT tiles); WIN: the whole linear window of a tile staged once.
+enum StageMode : int { STAGE_LINEAR = 0, STAGE_ROWS = 1, STAGE_WIN = 2 };
 
 struct MfmaArgs {
     const uint8_t* frags;
@@ -82,6 +84,7 @@ struct MfmaArgs {
     int32_t xcd_remap;     // 1: map consecutive tiles to the same XCD
     int32_t split_wb;      // row-layout tiles: scale blocks per work-group (1, 2 or 4)
     int32_t split_chunk;   // row-layout tiles: K-steps per chunk (a multiple of 8)
+    int32_t shm_bytes;     // dynamic LDS of the launch (the largest need over its clips)
     // single clip (grid launch)
     ClipArg clip;
     // batch (persistent launch)
@@ -89,7 +92,6 @@ struct MfmaArgs {
     const int32_t* tile_prefix; // device: tile_prefix[c] = first tile of clip c (n+1 entries)
     int32_t nclips;
     int32_t total_tiles;   // tiles over all clips and groups
-    int32_t* counter;      // device work counter pair {next, done}
 };
 
 struct DirectArgs {
@@ -106,6 +108,8 @@ hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
 hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, const int32_t* d_prefix,
                                int nclips, int total_tiles, hipStream_t s);
 // A = 32-frame blocks per wave (1, 2, 4); the third argument is unused.
+// persistent: 0 = one grid tile per work-group (single clip), 1 = persistent
+// batch kernel for any layout, 2 = persistent batch kernel for WIN tiles only.
 hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,
                        int grid, hipStream_t s);
 int mfma_max_lds_bytes();

@@ -86,16 +86,27 @@ static cwt_status current_device(int* dev, DeviceInfo* info) {
 }
 
 // ---------------------------------------------------------------------------
-// Kernel configurations.  MFMA: A = 32-frame blocks per wave (tile = 128*A
-// frames), chunk = K-steps staged per LDS buffer.
+// Kernel configurations.  MFMA: A = 32-frame blocks per wave, wb = preferred
+// 32-scale blocks per work-group for WIN tiles (tile = 32*A*(4/wb) frames),
+// chunk = upper bound of the K-steps per LDS buffer of chunked LINEAR tiles
+// (a multiple of 8; pick_chunk() shrinks it to what the LDS budget holds).
 struct MfmaCfg {
     int A;
+    int wb;
     int chunk;
 };
-// chunk is an upper bound (a multiple of 4); pick_chunk() shrinks it to what
-// the staging registers and the LDS budget hold for a given hop.
-static const MfmaCfg kMfmaCfgs[] = {{1, 64}, {2, 64}, {4, 32}, {1, 16}, {2, 16}, {4, 16}};
+static const MfmaCfg kMfmaCfgs[] = {
+    {4, 1, 32},   // 0: 512 frames x 1 block
+    {2, 1, 64},   // 1: 256 frames x 1 block
+    {1, 1, 64},   // 2: 128 frames x 1 block
+    {4, 4, 32},   // 3: 128 frames x 4 blocks
+    {2, 4, 64},   // 4:  64 frames x 4 blocks
+    {1, 4, 64},   // 5:  32 frames x 4 blocks
+    {2, 2, 64},   // 6: 128 frames x 2 blocks
+    {4, 2, 32},   // 7: 256 frames x 2 blocks
+};
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
+static const int kFp8Cfg = 5;   // the one FP8 configuration (see cfg_fits)
 
 static int elem_bytes(int dt) { return dt == DT_FP8 ? 1 : 2; }
 static int planes_of(int dt) { return dt == DT_BF16X3 ? 2 : 1; }
@@ -116,7 +127,8 @@ struct Staging {
     int64_t raw_bytes;  // LINEAR: the raw FP32 window buffer
 };
 
-static const int64_t kLdsBudget = 52 * 1024;   // three work-groups per CU
+static const int64_t kLdsBudget = 52 * 1024;   // chunked tiles: three work-groups per CU
+static const int64_t kWinBudget = 80 * 1024;   // WIN tiles: at least two work-groups per CU
 
 // The LINEAR layout for F frames and `chunk` K-steps.
 static Staging linear_staging(int dt, int hop, int F, int chunk) {
@@ -152,10 +164,9 @@ static Staging split_staging(int dt, int F, int chunk) {
     return s;
 }
 
-// A clip uses the LINEAR layout (128*A-frame tiles, one scale block each) when
-// that layout fits kLdsBudget at the smallest chunk; otherwise SPLIT tiles.
-// The choice depends only on (dtype, hop, A), so a clip is laid out the same
-// way alone and in any batch.
+// Chunked tiles: a clip uses the LINEAR layout (128*A-frame tiles, one scale
+// block each) when that layout fits kLdsBudget at the smallest chunk;
+// otherwise SPLIT tiles.
 static bool use_linear(int dt, int hop, int F) {
     Staging s = linear_staging(dt, hop, F, 8);
     return 2 * s.bytes + s.raw_bytes <= kLdsBudget;
@@ -176,9 +187,10 @@ static int pick_chunk(int dt, int hop, int F, int chunk_max) {
 struct SplitGeo {
     int wb, F, chunk, groups;
 };
+static int wb_cap(int nblocks) { return nblocks >= 3 ? 4 : (nblocks == 2 ? 2 : 1); }
 static SplitGeo split_geo(int dt, int nblocks) {
     SplitGeo g;
-    g.wb = nblocks >= 3 ? 4 : (nblocks == 2 ? 2 : 1);
+    g.wb = wb_cap(nblocks);
     g.F = 32 * (4 / g.wb);
     g.groups = (nblocks + g.wb - 1) / g.wb;
     g.chunk = 8;
@@ -189,6 +201,8 @@ static SplitGeo split_geo(int dt, int nblocks) {
         }
     return g;
 }
+
+static int log2_small(int v) { return v >= 4 ? 2 : (v >= 2 ? 1 : 0); }
 
 // ---------------------------------------------------------------------------
 // Wavelet bank: device-resident, shared by plans with the same key.
@@ -209,6 +223,7 @@ struct Bank {
     MfmaBlock* d_blocks = nullptr;
     int64_t frag_bytes = 0;
     int Mmax = 0;
+    int win_steps[3] = {0, 0, 0};      // widest union K range of a group of 1, 2, 4 blocks
 
     ~Bank() {
         if (d_dtaps) (void)hipFree(d_dtaps);
@@ -307,6 +322,17 @@ static cwt_status build_bank(int dt, int device, const std::vector<double>& scal
             bk->blocks.push_back(B);
         }
         bk->frag_bytes = off;
+        for (int l = 0; l < 3; ++l) {
+            const int wb = 1 << l;
+            for (int b0 = 0; b0 < nbk; b0 += wb) {
+                int glo = bk->blocks[b0].lo, ghi = bk->blocks[b0].hi;
+                for (int b = b0 + 1; b < std::min(nbk, b0 + wb); ++b) {
+                    glo = std::min(glo, bk->blocks[b].lo);
+                    ghi = std::max(ghi, bk->blocks[b].hi);
+                }
+                bk->win_steps[l] = std::max(bk->win_steps[l], ghi - glo + 1);
+            }
+        }
         HIP_TRY(hipMalloc(&d_alpha, sizeof(double) * S), "alpha");
         std::unique_ptr<double, void (*)(double*)> g2(d_alpha, [](double* p) { (void)hipFree(p); });
         HIP_TRY(hipMemcpy(d_alpha, alpha.data(), sizeof(double) * S, hipMemcpyHostToDevice), "alpha copy");
@@ -342,6 +368,14 @@ static cwt_status acquire_bank(int dt, int device, const std::vector<double>& sc
 
 // ---------------------------------------------------------------------------
 // Plans.
+// One clip's tile layout (see clip_layout()).
+struct ClipLayout {
+    Staging s;
+    int wb = 1;          // scale blocks per work-group
+    int F = 0;           // frames per tile
+    int64_t groups = 0;  // work-group tiles per frame tile
+};
+
 struct cwt_plan_s {
     double fs;
     int hop;
@@ -352,6 +386,8 @@ struct cwt_plan_s {
     int cus = 0;
     std::string arch;
     std::shared_ptr<Bank> bank;
+    ClipLayout lay;      // MFMA layout under cfg ...
+    int lay_chunk = 8;   // ... for chunked LINEAR tiles of this chunk
 };
 
 static std::string tune_key(const cwt_plan_s* p, int64_t len) {
@@ -401,34 +437,85 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
     std::rename(tmp.c_str(), path);
 }
 
-// Default configuration: the widest tile (A = 4, 2, 1) whose LINEAR layout fits
-// the LDS budget; FP8 always uses A = 1.  Large hops fall through to A = 1 and
-// SPLIT tiles.
+// Default configuration by hop (measured on MI355X, 128 linear scales, 10 s
+// clips): every hop does best with one window shared by four scale blocks;
+// the frame tile narrows as the hop grows (128 frames at hop <= 2, 64 up to
+// hop 8, 32 beyond).  FP8 has one configuration.
 static int default_cfg(int dt, int hop) {
-    if (dt == DT_FP32 || dt == DT_FP8) return 0;      // {1, 64}
-    if (use_linear(dt, hop, 512)) return 2;          // {4, 32}
-    if (use_linear(dt, hop, 256)) return 1;          // {2, 64}
-    return 0;                                         // {1, 64}
+    if (dt == DT_FP32) return 0;
+    if (dt == DT_FP8) return kFp8Cfg;
+    if (hop <= 2) return 3;
+    if (hop <= 8) return 4;
+    return 5;
 }
 
 static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
+    (void)hop;
     if (p->dt == DT_FP32) return cfg == 0;
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
+    // FP8 scales the signal per tile; one fixed tile geometry keeps every
+    // clip's result independent of the configuration and of its batch.
+    if (p->dt == DT_FP8) return cfg == kFp8Cfg;
+    return true;   // a layout always exists: WIN, chunked LINEAR or SPLIT tiles
+}
+
+// Per-clip layout under a configuration: WIN tiles with the first wb >= cfg.wb
+// (up to the bank's block count) whose whole window fits kWinBudget; else
+// chunked LINEAR tiles if they fit kLdsBudget; else SPLIT tiles.  The choice
+// depends only on (dtype, bank, hop, configuration), never on the batch.
+static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c, int chunk) {
+    ClipLayout L;
+    const int nblk = (int)bk.blocks.size(), cap = wb_cap(nblk);
+    for (int wb = std::min(c.wb, cap); wb <= cap; wb *= 2) {
+        const int F = 32 * c.A * (4 / wb);
+        Staging s = linear_staging(dt, hop, F, bk.win_steps[log2_small(wb)]);
+        if (s.bytes <= kWinBudget) {
+            s.mode = STAGE_WIN;
+            s.raw_bytes = 0;
+            L.s = s;
+            L.wb = wb;
+            L.F = F;
+            L.groups = (nblk + wb - 1) / wb;
+            return L;
+        }
+    }
+    if (use_linear(dt, hop, 128 * c.A)) {
+        L.s = linear_staging(dt, hop, 128 * c.A, chunk);
+        L.wb = 1;
+        L.F = 128 * c.A;
+        L.groups = nblk;
+        return L;
+    }
+    const SplitGeo sg = split_geo(dt, nblk);
+    L.s = split_staging(dt, sg.F, sg.chunk);
+    L.wb = sg.wb;
+    L.F = sg.F;
+    L.groups = sg.groups;
+    return L;
+}
+
+// Dynamic LDS a layout needs: one window (WIN), two buffers plus the raw
+// window (LINEAR), two row buffers (ROWS).
+static int64_t layout_lds(const ClipLayout& L) {
+    if (L.s.mode == STAGE_WIN) return L.s.bytes;
+    return 2 * L.s.bytes + L.s.raw_bytes;
+}
+
+// Set the plan's configuration and cache its layout.
+static void set_cfg(cwt_plan_s* p, int cfg) {
+    p->cfg = cfg;
+    if (p->dt == DT_FP32) return;
     const MfmaCfg& c = kMfmaCfgs[cfg];
-    // FP8 scales the signal per tile; a fixed tile keeps every clip's result
-    // independent of the configuration and of the batch it runs in.
-    if (p->dt == DT_FP8 && c.A != 1) return false;
-    (void)hop;
-    return true;   // a layout always exists: LINEAR within budget, or SPLIT tiles
+    p->lay_chunk = pick_chunk(p->dt, p->hop, 128 * c.A, c.chunk);
+    p->lay = clip_layout(p->dt, *p->bank, p->hop, c, p->lay_chunk);
 }
 
 // ---------------------------------------------------------------------------
 // Launch of one clip.
-// One clip's kernel record.  MFMA: LINEAR tiles of F = 128*A frames (chunk
-// `chunk`) or SPLIT tiles; *bytes_out/*raw_out receive its LDS needs and
-// *tiles_out its work-group tiles (frame tiles x block groups).
-static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int A, int chunk,
-                         int64_t* bytes_out, int64_t* raw_out, int64_t* tiles_out) {
+// One clip's kernel record and, for the MFMA path, its layout (*lay) and its
+// work-group tiles (*tiles_out: frame tiles x block groups).
+static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int cfg, int chunk,
+                         ClipLayout* lay, int64_t* tiles_out) {
     ClipArg c;
     std::memset(&c, 0, sizeof(c));
     c.x = x;
@@ -436,31 +523,21 @@ static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float
     c.len = len;
     c.hop = p->hop;
     c.K = (len + p->hop - 1) / p->hop;
+    c.wb = 1;
     if (p->dt == DT_FP32) {
         c.ntile = (int32_t)((c.K + kDirectFrames - 1) / kDirectFrames);
         if (tiles_out) *tiles_out = (int64_t)c.ntile * (((int64_t)p->bank->dgroups.size() + kDirectWaves - 1) / kDirectWaves);
         return c;
     }
-    const int nblk = (int)p->bank->blocks.size();
-    const int F = 128 * A;
-    Staging s;
-    int64_t tiles;
-    if (use_linear(p->dt, p->hop, F)) {
-        s = linear_staging(p->dt, p->hop, F, chunk);
-        c.ntile = (int32_t)((c.K + F - 1) / F);
-        tiles = (int64_t)c.ntile * nblk;
-    } else {
-        SplitGeo sg = split_geo(p->dt, nblk);
-        s = split_staging(p->dt, sg.F, sg.chunk);
-        c.ntile = (int32_t)((c.K + sg.F - 1) / sg.F);
-        tiles = (int64_t)c.ntile * sg.groups;
-    }
-    c.mode = s.mode;
-    c.copies = s.copies;
-    c.swz = s.swz;
-    if (bytes_out) *bytes_out = s.bytes;
-    if (raw_out) *raw_out = s.raw_bytes;
-    if (tiles_out) *tiles_out = tiles;
+    const bool cached = cfg == p->cfg && (p->lay.s.mode != STAGE_LINEAR || chunk == p->lay_chunk);
+    const ClipLayout L = cached ? p->lay : clip_layout(p->dt, *p->bank, p->hop, kMfmaCfgs[cfg], chunk);
+    c.ntile = (int32_t)((c.K + L.F - 1) / L.F);
+    c.mode = L.s.mode;
+    c.copies = L.s.copies;
+    c.swz = L.s.swz;
+    c.wb = L.wb;
+    if (lay) *lay = L;
+    if (tiles_out) *tiles_out = (int64_t)c.ntile * L.groups;
     return c;
 }
 
@@ -475,14 +552,13 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
         a.groups = bk.d_dgroups;
         a.ngroups = (int)bk.dgroups.size();
         a.signed_out = p->signed_out;
-        a.clip = make_clip(p, x, len, out, 1, 8, nullptr, nullptr, &tiles);
+        a.clip = make_clip(p, x, len, out, 0, 8, nullptr, &tiles);
         a.xcd_remap = 1;
         HIP_TRY(launch_direct(a, stream), "direct launch");
         return CWT_OK;
     }
     const MfmaCfg& c = kMfmaCfgs[cfg];
-    const int F = 128 * c.A;
-    const int chunk = pick_chunk(p->dt, p->hop, F, c.chunk);
+    const int chunk = pick_chunk(p->dt, p->hop, 128 * c.A, c.chunk);
     const SplitGeo sg = split_geo(p->dt, (int)bk.blocks.size());
     MfmaArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -491,13 +567,14 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
     a.ngroups = (int)bk.blocks.size();
     a.signed_out = p->signed_out;
     a.chunk_steps = chunk;
-    a.frames = F;
+    a.frames = 128 * c.A;
     a.split_wb = sg.wb;
     a.split_chunk = sg.chunk;
-    int64_t bytes = 0, raw = 0;
-    a.clip = make_clip(p, x, len, out, c.A, chunk, &bytes, &raw, &tiles);
-    a.buf_bytes = (int32_t)bytes;
-    a.raw_bytes = (int32_t)raw;
+    ClipLayout L;
+    a.clip = make_clip(p, x, len, out, cfg, chunk, &L, &tiles);
+    a.buf_bytes = L.s.mode == STAGE_WIN ? 0 : (int32_t)L.s.bytes;
+    a.raw_bytes = (int32_t)L.s.raw_bytes;
+    a.shm_bytes = (int32_t)layout_lds(L);
     a.xcd_remap = 1;
     if (tiles > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
     HIP_TRY(launch_mfma(p->dt, c.A, 1, a, 0, (int)tiles, stream), "mfma launch");
@@ -511,6 +588,8 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t copy_node = nullptr;
     hipGraphNode_t kernel_node = nullptr;
+    MfmaArgs args;            // kernel arguments of the last replay
+    size_t copy_bytes = 0;    // descriptor bytes of the last replay
 };
 
 struct cwt_batch_s {
@@ -523,7 +602,6 @@ struct cwt_batch_s {
     bool used[2] = {false, false};
     int flip = 0;
     uint8_t* d_desc = nullptr;
-    int32_t* d_counter = nullptr;
     hipStream_t cap_stream = nullptr;
     std::map<std::tuple<int, int, int, int, int, int>, GraphEntry> graphs;
     std::mutex mu;
@@ -541,7 +619,6 @@ struct cwt_batch_s {
             if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
         }
         if (d_desc) (void)hipFree(d_desc);
-        if (d_counter) (void)hipFree(d_counter);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
@@ -563,17 +640,21 @@ static cwt_status batch_init(cwt_batch_s* b, int max_clips) {
         HIP_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming), "batch event");
     }
     HIP_TRY(hipMalloc(&b->d_desc, b->desc_cap), "device descriptors");
-    HIP_TRY(hipMalloc(&b->d_counter, 2 * sizeof(int32_t)), "work counter");
-    HIP_TRY(hipMemset(b->d_counter, 0, 2 * sizeof(int32_t)), "work counter init");
     HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "capture stream");
     HIP_TRY(hipDeviceSynchronize(), "batch init");
     return CWT_OK;
 }
 
 // Persistent grid: enough work-groups to fill every CU at the kernel's occupancy.
-static int persistent_grid(int cus, int dt, int A, int nb, int64_t lds_bytes) {
-    int per_cu = mfma_occupancy(dt, A, nb, 1, (size_t)lds_bytes);
-    return cus * std::max(1, per_cu);
+// Persistent grid: every work-group resident (CUs x occupancy), reduced to
+// the nearest size coprime with `groups` (the lcm of the clips' block-group
+// counts) so that the static tile stride rotates each work-group through
+// the groups.
+static int persistent_grid(int cus, int dt, int A, int kind, int64_t lds_bytes, int64_t groups) {
+    const int per_cu = mfma_occupancy(dt, A, 0, kind, (size_t)lds_bytes);
+    int g = cus * std::max(1, per_cu);
+    while (g > 1 && gcd64(g, std::max<int64_t>(1, groups)) != 1) --g;
+    return g;
 }
 
 static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float* const* xs,
@@ -599,22 +680,30 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
     const Bank& bk = *p0->bank;
 
-    // One configuration for the whole launch (the first plan's) and one LINEAR
-    // chunk: the largest for which the worst clip's LDS (operand buffers plus
-    // raw window, maximised over the clips) fits the budget.  SPLIT clips have
-    // a fixed geometry per bank.
+    // One configuration for the whole launch (the first plan's) and one chunk
+    // for its chunked LINEAR clips: the largest for which the worst such clip's
+    // LDS (operand buffers plus raw window) fits the budget.  WIN and SPLIT
+    // clips have a fixed geometry per (bank, hop, configuration).
     const bool fp32 = p0->dt == DT_FP32;
     const int cfg = p0->cfg;
-    const MfmaCfg c = fp32 ? MfmaCfg{1, 8} : kMfmaCfgs[cfg];
+    const MfmaCfg c = kMfmaCfgs[fp32 ? 0 : cfg];
     int chunk = 8;
-    if (!fp32) {
+    bool any_linear = false;
+    for (int i = 0; i < n && !fp32; ++i)
+        if (lens[i] > 0) {
+            const ClipLayout& L = plans[i]->cfg == cfg ? plans[i]->lay
+                                  : clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk);
+            any_linear = any_linear || L.s.mode == STAGE_LINEAR;
+        }
+    if (any_linear) {
         for (int ch = c.chunk; ch >= 8; ch -= 8) {
             int64_t mb = 0, mr = 0;
             for (int i = 0; i < n; ++i) {
-                if (lens[i] == 0 || !use_linear(p0->dt, plans[i]->hop, 128 * c.A)) continue;
-                Staging st = linear_staging(p0->dt, plans[i]->hop, 128 * c.A, ch);
-                mb = std::max(mb, st.bytes);
-                mr = std::max(mr, st.raw_bytes);
+                if (lens[i] == 0) continue;
+                const ClipLayout L = clip_layout(p0->dt, bk, plans[i]->hop, c, ch);
+                if (L.s.mode != STAGE_LINEAR) continue;
+                mb = std::max(mb, L.s.bytes);
+                mr = std::max(mr, L.s.raw_bytes);
             }
             if (2 * mb + mr <= kLdsBudget) {
                 chunk = ch;
@@ -635,13 +724,17 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     // Longest first (most tiles first) so the persistent grid drains evenly.
     std::vector<ClipArg> clips(n);
     std::vector<int64_t> ctiles(n, 0);
-    int64_t maxbytes = 16;
-    int64_t maxraw = 0;
+    int64_t maxbuf = 16, maxraw = 0, maxwin = 0;
     for (int i : order) {
-        int64_t bytes = 0, raw = 0;
-        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], c.A, chunk, &bytes, &raw, &ctiles[i]);
-        maxbytes = std::max(maxbytes, bytes);
-        maxraw = std::max(maxraw, raw);
+        ClipLayout L;
+        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], fp32 ? 0 : cfg, chunk, &L, &ctiles[i]);
+        if (fp32) continue;
+        if (L.s.mode == STAGE_WIN) {
+            maxwin = std::max(maxwin, L.s.bytes);
+        } else {
+            maxbuf = std::max(maxbuf, L.s.bytes);
+            maxraw = std::max(maxraw, L.s.raw_bytes);
+        }
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return ctiles[a] > ctiles[bq]; });
     const int nc = (int)order.size();
@@ -686,30 +779,42 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.frames = 128 * c.A;
     a.split_wb = sg.wb;
     a.split_chunk = sg.chunk;
-    a.buf_bytes = (int32_t)maxbytes;
+    a.buf_bytes = (int32_t)maxbuf;
     a.raw_bytes = (int32_t)maxraw;
+    a.shm_bytes = (int32_t)std::max(2 * maxbuf + maxraw, maxwin);
     a.xcd_remap = 0;
     // The descriptor pointers are fixed device addresses; counts live in the header.
     a.clips = (const ClipArg*)(b->d_desc + 16);
     a.tile_prefix = (const int32_t*)(b->d_desc + 16 + sizeof(ClipArg) * nc);
     a.nclips = nc;
     a.total_tiles = (int32_t)total;
-    a.counter = b->d_counter;
-    const int grid = persistent_grid(b->cus, p0->dt, c.A, 1, 2 * maxbytes + maxraw);
+    // WIN-only batches run the kernel compiled for the WIN register budget.
+    bool all_win = true;
+    for (int j = 0; j < nc; ++j) all_win = all_win && hc[j].mode == STAGE_WIN;
+    const int pkind = all_win ? 2 : 1;
+    int64_t groups_lcm = 1;
+    for (int j = 0; j < nc; ++j) {
+        const int64_t ng = hc[j].mode == STAGE_WIN ? (a.ngroups + hc[j].wb - 1) / hc[j].wb
+                           : hc[j].mode == STAGE_LINEAR ? a.ngroups : sg.groups;
+        groups_lcm = groups_lcm / gcd64(groups_lcm, ng) * ng;
+        if (groups_lcm > 4096) groups_lcm = 4096;   // bounded: a heuristic, not a requirement
+    }
+    const int grid = (int)std::min<int64_t>(persistent_grid(b->cus, p0->dt, c.A, pkind, a.shm_bytes, groups_lcm),
+                                            total);
 
     if (!use_graph) {
         HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
-        HIP_TRY(launch_mfma(p0->dt, c.A, 1, a, 1, grid, stream), "persistent launch");
+        HIP_TRY(launch_mfma(p0->dt, c.A, 1, a, pkind, grid, stream), "persistent launch");
     } else {
-        // Kernel arguments that vary per batch (nclips, total tiles, prefix
-        // address) are part of the captured node, so graphs are cached per
-        // (shape) and their kernel node parameters refreshed before replay.
-        auto key = std::make_tuple(p0->dt, c.A, (int)maxraw, (int)maxbytes, grid, chunk);
+        // One graph per (shape, pinned buffer): the descriptor copy's source is
+        // then fixed, and its size and the kernel arguments (counts, chunk)
+        // are refreshed only when they differ from the previous replay.
+        auto key = std::make_tuple(p0->dt, c.A, (int)a.shm_bytes, grid, pkind, slot);
         GraphEntry& ge = b->graphs[key];
         if (!ge.exec) {
             HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
             hipError_t e1 = hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream);
-            hipError_t e2 = launch_mfma(p0->dt, c.A, 1, a, 1, grid, b->cap_stream);
+            hipError_t e2 = launch_mfma(p0->dt, c.A, 1, a, pkind, grid, b->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e3 = hipStreamEndCapture(b->cap_stream, &g);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -730,16 +835,23 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
             }
             if (!ge.copy_node || !ge.kernel_node) return fail(CWT_ERR_INTERNAL, "unexpected graph shape");
             HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0), "graph instantiate");
+            std::memcpy(&ge.args, &a, sizeof(a));   // padding included, for the memcmp below
+            ge.copy_bytes = used_bytes;
         } else {
-            HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, b->d_desc, host, used_bytes,
-                                                      hipMemcpyHostToDevice), "graph copy update");
-            // Refresh the kernel node's argument block.
-            hipKernelNodeParams kp;
-            HIP_TRY(hipGraphKernelNodeGetParams(ge.kernel_node, &kp), "kernel node params");
-            void* args[1] = {&a};
-            kp.kernelParams = args;
-            kp.extra = nullptr;
-            HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.kernel_node, &kp), "kernel node update");
+            if (ge.copy_bytes != used_bytes) {
+                HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, b->d_desc, host, used_bytes,
+                                                          hipMemcpyHostToDevice), "graph copy update");
+                ge.copy_bytes = used_bytes;
+            }
+            if (std::memcmp(&ge.args, &a, sizeof(a)) != 0) {
+                hipKernelNodeParams kp;
+                HIP_TRY(hipGraphKernelNodeGetParams(ge.kernel_node, &kp), "kernel node params");
+                void* args[1] = {&a};
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.kernel_node, &kp), "kernel node update");
+                std::memcpy(&ge.args, &a, sizeof(a));
+            }
         }
         HIP_TRY(hipGraphLaunch(ge.exec, stream), "graph launch");
     }
@@ -807,19 +919,19 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
             std::call_once(attr_once, [&] { ae = mfma_init_attributes(); });
             if (ae != hipSuccess) return fail(CWT_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(ae));
         }
-        p->cfg = default_cfg(p->dt, hop);
+        set_cfg(p.get(), default_cfg(p->dt, hop));
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto m = read_tune_cache();
             // the length bucket of 10 s at 16 kHz is the default class
             auto it = m.find(tune_key(p.get(), 160000));
-            if (it != m.end() && cfg_fits(p.get(), it->second, hop)) p->cfg = it->second;
+            if (it != m.end() && cfg_fits(p.get(), it->second, hop)) set_cfg(p.get(), it->second);
         }
         if (!cfg_fits(p.get(), p->cfg, hop)) {
             bool found = false;
             for (int c = 0; c < (p->dt == DT_FP32 ? 1 : kNumMfmaCfgs); ++c)
                 if (cfg_fits(p.get(), c, hop)) {
-                    p->cfg = c;
+                    set_cfg(p.get(), c);
                     found = true;
                     break;
                 }
@@ -946,7 +1058,7 @@ int32_t cwt_plan_num_configs(cwt_plan_t plan) {
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index) {
     if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
     if (!cfg_fits(plan, index, plan->hop)) return fail(CWT_ERR_INVALID_ARG, "configuration does not fit this plan");
-    plan->cfg = index;
+    set_cfg(plan, index);
     return CWT_OK;
 }
 
@@ -991,7 +1103,7 @@ cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out) {
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        plan->cfg = best;
+        set_cfg(plan, best);
         if (chosen_out) *chosen_out = best;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto m = read_tune_cache();

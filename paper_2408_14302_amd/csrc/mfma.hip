@@ -9,18 +9,19 @@
 // with KS = 16 (BF16/FP16: v_mfma_f32_32x32x16_*) or 64 (FP8:
 // v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales).  Accumulation is FP32.
 //
-// Signal staging.  The taps are walked in chunks of `chunk_steps` K-steps.  For
-// each chunk the work-group converts the needed samples (zero outside
-// [0, len)) to the operand type and writes them to one of two LDS buffers
-// while the other buffer feeds the MFMAs.  Two layouts:
-//   LINEAR  the window x~[k0*hop + KS*ks_c + p], p = 0 .. (F-1)*hop + KS*chunk,
-//           kept in `copies` copies shifted by multiples of gcd(hop, U) so every
-//           lane's 16-byte read is aligned (U = elements per 16 bytes); for
-//           power-of-two hops an XOR swizzle of the 16-byte unit index spreads
-//           the frame-strided reads over the LDS banks.
-//   ROWS    one padded row per frame holding x~[(k0+f)*hop + KS*ks_c + c]; used
-//           (with small tiles whose waves take different scale blocks) when the
-//           frames are so far apart that the linear window would not fit.
+// Signal staging (samples outside [0, len) are zero):
+//   WIN     the tile's whole window x~[k0*hop + KS*glo + p] over the K range of
+//           its scale blocks, converted once from global memory and shared by
+//           up to four blocks (one per wave); kept in `copies` copies shifted
+//           by multiples of gcd(hop, U) so every lane's 16-byte read is aligned
+//           (U = elements per 16 bytes); for power-of-two hops an XOR swizzle
+//           of the 16-byte unit index spreads the frame-strided reads over the
+//           LDS banks.  The default whenever the window fits.
+//   LINEAR  the same layout, walked in chunks of `chunk_steps` K-steps through
+//           two LDS buffers fed from a raw FP32 window (very wide scales at
+//           small hops).
+//   ROWS    one padded row per frame holding x~[(k0+f)*hop + KS*ks_c + c],
+//           chunked (frames so far apart that no window fits).
 // Summation order per coefficient: K-steps ascending, fixed per block, so the
 // result does not depend on the tile, the launch shape or the batch.
 #include "cwt_internal.h"
@@ -79,37 +80,6 @@ __device__ __forceinline__ f32x16 mma_all(const Frag<DT>& t, const Frag<DT>& x, 
     }
 }
 
-// Convert U consecutive float samples into one 16-byte unit per plane.
-template <int DT>
-__device__ __forceinline__ void pack_unit(const float* v, float beta, i32x4* out) {
-    if constexpr (DT == DT_BF16 || DT == DT_BF16X3) {
-        bf16x8 h;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
-        out[0] = __builtin_bit_cast(i32x4, h);
-        if constexpr (DT == DT_BF16X3) {
-            bf16x8 l;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) l[e] = (__bf16)(v[e] - (float)h[e]);  // exact residual
-            out[1] = __builtin_bit_cast(i32x4, l);
-        }
-    } else if constexpr (DT == DT_FP16) {
-        f16x8 h;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = (_Float16)v[e];
-        out[0] = __builtin_bit_cast(i32x4, h);
-    } else {
-        i32x4 r;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            int word = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w] * beta, v[4 * w + 1] * beta, 0, false);
-            word = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w + 2] * beta, v[4 * w + 3] * beta, word, true);
-            r[w] = word;
-        }
-        out[0] = r;
-    }
-}
-
 // Per-tile staging geometry (uniform across the work-group).
 struct Geo {
     int mode, copies, gh, cs, swz, rs;  // see host: cs/rs in 16-byte units
@@ -125,7 +95,7 @@ __device__ __forceinline__ Geo make_geo(const ClipArg& c, int F, int chunk) {
     g.copies = c.copies;
     g.gh = T::U / c.copies;
     g.swz = c.swz;
-    if (g.mode == STAGE_LINEAR) {
+    if (g.mode != STAGE_ROWS) {
         int pmax = (F - 1) * c.hop + T::KS * chunk - 1;
         g.len_u = ((pmax / T::U + 1) + 15) & ~15;
         g.cs = g.len_u + (g.copies > 1 ? 16 / g.copies : 0);
@@ -259,12 +229,12 @@ template <int DT>
 __device__ constexpr int stage_floats() { return 32; }
 
 template <int DT>
-__device__ __forceinline__ bool multi_copy(const Geo& g) { return g.mode == STAGE_LINEAR && g.copies > 1; }
+__device__ __forceinline__ bool multi_copy(const Geo& g) { return g.mode != STAGE_ROWS && g.copies > 1; }
 
 template <int DT>
 __device__ __forceinline__ int stage_units(const Geo& g, int F, int chunk) {
     using T = Tr<DT>;
-    return g.mode == STAGE_LINEAR ? g.len_u : F * (T::KS * chunk / T::U);
+    return g.mode != STAGE_ROWS ? g.len_u : F * (T::KS * chunk / T::U);
 }
 
 // Source sample of single-span unit q and its 16-byte LDS unit.
@@ -272,7 +242,7 @@ template <int DT>
 __device__ __forceinline__ void unit_geo(const ClipArg& c, const Geo& g, int chunk, int64_t k0, int ks_c, int q,
                                          int64_t& j, int& dst) {
     using T = Tr<DT>;
-    if (g.mode == STAGE_LINEAR) {
+    if (g.mode != STAGE_ROWS) {
         j = k0 * c.hop + (int64_t)T::KS * ks_c + (int64_t)q * T::U;
         dst = swizzle(q, g.swz);
     } else {
@@ -562,14 +532,15 @@ __device__ __forceinline__ void mma_frags(const Frag<DT>& t, const Frag<DT> (&x)
 
 // Per-lane LDS byte offset of step 0 of a chunk (within one buffer) and, for
 // the swizzled layout, the logical 16-byte unit of step 0.
+// fb0 is the wave's first 32-frame block within the tile.
 template <int DT, int A, int LM>
-__device__ __forceinline__ void lane_bases(const ClipArg& c, const Geo& g, int (&base)[A], int (&unit0)[A]) {
+__device__ __forceinline__ void lane_bases(const ClipArg& c, const Geo& g, int fb0, int (&base)[A], int (&unit0)[A]) {
     using T = Tr<DT>;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int n = lane & 31, hg = lane >> 5;
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
-        const int f = 32 * (A * w + fa) + n;
+        const int f = 32 * (fb0 + fa) + n;
         if constexpr (LM == LM_ROWS) {
             base[fa] = (f * g.rs + hg * T::LU) * 16;
             unit0[fa] = 0;
@@ -582,10 +553,6 @@ __device__ __forceinline__ void lane_bases(const ClipArg& c, const Geo& g, int (
     }
 }
 
-// The MFMAs of one chunk (ns steps, a multiple of 8) from LDS buffer `cur`.
-// Tap fragments (from L2) are loaded eight steps ahead into two banks of four
-// register sets, signal fragments (from LDS) one step ahead into a ring of two;
-// every slot is a compile-time constant.
 // The MFMAs of steps ks_c+d0 .. ks_c+d0+ns-1 (ns a multiple of 8) of the chunk
 // starting at ks_c, from LDS buffer `cur`.  Tap fragments (from L2) are loaded
 // eight steps ahead into two banks of four register sets, signal fragments
@@ -632,7 +599,7 @@ __device__ __forceinline__ void tile_loop_linear(const MfmaArgs& a, const ClipAr
     const int swz = g.swz < 0 ? 31 : g.swz;
     uint8_t* raw = lds + 2 * a.buf_bytes;
     int base[A], unit0[A];
-    lane_bases<DT, A, LM>(c, g, base, unit0);
+    lane_bases<DT, A, LM>(c, g, A * (threadIdx.x >> 6), base, unit0);
     auto jb_of = [&](int ks_c) { return k0 * c.hop + (int64_t)T::KS * ks_c; };
     auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
 
@@ -747,7 +714,6 @@ __device__ __forceinline__ void process_tile_split(const MfmaArgs& a, const Clip
 // LINEAR work-group tile: F = 128*A consecutive frames of one clip against one
 // 32-scale block.  Each wave owns A 32-frame blocks; every K-step is A MFMAs
 // sharing one tap fragment.
-// LINEAR tile.
 template <int DT, int A>
 __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c, int tile, int blk,
                                              uint8_t* lds, float* red) {
@@ -795,6 +761,147 @@ __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c
     }
 }
 
+// Register budget of the WIN kernels: W waves per SIMD (512 / W registers per
+// lane), enough to overlap one work-group's staging with another's MFMAs, and
+// SF staging floats in flight per thread.  Two-plane (BF16x3) and FP8 tap
+// fragments are twice as wide.
+template <int DT, int A>
+struct WinOcc {
+    static constexpr bool wide = DT == DT_BF16X3 || DT == DT_FP8;
+    static constexpr int W = wide ? (A == 4 ? 1 : 2) : (A == 4 ? 3 : 4);
+    static constexpr int SF = 32;
+};
+
+// ---------------------------------------------------------------------------
+// WIN staging: the whole window, straight from global memory.  Each pass
+// issues the loads of R units per thread (SF floats in flight) before it
+// converts and writes any of them.
+template <int DT, int SF>
+__device__ __forceinline__ void win_stage(const ClipArg& c, const Geo& g, int64_t jb, bool al16, float beta,
+                                          uint8_t* lds) {
+    constexpr int U = Tr<DT>::U;
+    if (g.copies > 1) {
+        constexpr int SP = 2 * U, R = SF / SP > 0 ? SF / SP : 1;
+        for (int u0 = threadIdx.x; u0 < g.len_u; u0 += 256 * R) {
+            float v[R][SP];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int uu = u0 + 256 * i;
+                if (uu < g.len_u) load_span<SP, 0>(c.x, c.len, jb + (int64_t)uu * U, al16, v[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int uu = u0 + 256 * i;
+                if (uu < g.len_u) {
+                    Packed<DT, SP> pk;
+                    pack_span<DT, SP, 0>(v[i], beta, pk);
+                    put_copies<DT, SP>(pk, g, swizzle(uu, g.swz), lds, 0);
+                }
+            }
+        }
+    } else {
+        constexpr int R = SF / U > 0 ? SF / U : 1;
+        for (int u0 = threadIdx.x; u0 < g.len_u; u0 += 256 * R) {
+            float v[R][U];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int uu = u0 + 256 * i;
+                if (uu < g.len_u) load_span<U, 0>(c.x, c.len, jb + (int64_t)uu * U, al16, v[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int uu = u0 + 256 * i;
+                if (uu < g.len_u) {
+                    Packed<DT, U> pk;
+                    pack_span<DT, U, 0>(v[i], beta, pk);
+                    i32x4 u[Tr<DT>::PLANES];
+#pragma unroll
+                    for (int p = 0; p < Tr<DT>::PLANES; ++p) u[p] = window<DT, U, 0>(pk, p);
+                    put_unit<DT>(lds, swizzle(uu, g.swz) * 16, g.plane_bytes, u);
+                }
+            }
+        }
+    }
+}
+
+// WIN tile: F = 32*A*(4/WB) consecutive frames against the WB consecutive
+// 32-scale blocks of group grp.  Wave w takes block slot (w + tile) % WB of
+// the group (rotated so that the widest block does not always land on the
+// same SIMD) and the A frame blocks A*(w / WB) ..; it runs only its own
+// block's K-steps over the shared window.
+template <int DT, int A>
+__device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
+                                                 uint8_t* lds, float* red) {
+    using T = Tr<DT>;
+    const int WB = c.wb, WF = kMfmaWaves / WB, F = 32 * A * WF;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n = lane & 31, hg = lane >> 5;
+    const int wf = w / WB, wb = w - wf * WB;
+    const int64_t k0 = (int64_t)tile * F;
+    const int b0 = grp * WB, nb = min(WB, a.ngroups - b0);
+    int glo = a.blocks[b0].lo, ghi = a.blocks[b0].hi;
+    for (int i = 1; i < nb; ++i) {
+        glo = min(glo, a.blocks[b0 + i].lo);
+        ghi = max(ghi, a.blocks[b0 + i].hi);
+    }
+    const int slot = (wb + tile) % WB;
+    const bool has = slot < nb;
+    const MfmaBlock* __restrict__ B = a.blocks + b0 + (has ? slot : 0);
+    const int lo = B->lo, hi = B->hi;
+    const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
+    const Geo g = make_geo<DT>(c, F, ghi - glo + 1);
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
+    float beta = 1.0f;
+    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
+    auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
+
+    // the first eight tap fragments are in flight while the window is staged
+    Frag<DT> ta[4], tb[4];
+    if (has) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            load_tap<DT>(tap(lo + j), lane, ta[j]);
+            load_tap<DT>(tap(lo + 4 + j), lane, tb[j]);
+        }
+    }
+    win_stage<DT, WinOcc<DT, A>::SF>(c, g, k0 * c.hop + (int64_t)T::KS * glo, al16, beta, lds);
+    __syncthreads();
+    if (!has) return;
+
+    f32x16 acc[A];
+#pragma unroll
+    for (int fa = 0; fa < A; ++fa)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
+    int base[A], unit0[A];
+    if (g.swz >= 0) {
+        lane_bases<DT, A, LM_LINEAR_SWZ>(c, g, A * wf, base, unit0);
+        compute_chunk<DT, A, LM_LINEAR_SWZ>(lds, g, g.swz, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase,
+                                            ta, tb, acc);
+    } else {
+        lane_bases<DT, A, LM_LINEAR>(c, g, A * wf, base, unit0);
+        compute_chunk<DT, A, LM_LINEAR>(lds, g, 31, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase, ta, tb,
+                                        acc);
+    }
+
+    const float inv_beta = 1.0f / beta;
+#pragma unroll
+    for (int fa = 0; fa < A; ++fa) {
+        const int64_t k = k0 + 32 * (A * wf + fa) + n;
+        if (k >= c.K) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
+            const int row = B->rows[rr];
+            if (row < 0) continue;
+            float val = acc[fa][v];
+            if constexpr (DT == DT_FP8) val = val * (B->inv_alpha[rr] * inv_beta);
+            if (!a.signed_out) val = fabsf(val);
+            __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
+        }
+    }
+}
+
 __device__ __forceinline__ int xcd_remap(int id, int n) {
     // Work-groups are dealt to the 8 XCDs round-robin; give each XCD a
     // contiguous range of tiles so neighbouring tiles share its L2.
@@ -825,24 +932,48 @@ __global__ __launch_bounds__(256) void k_mfma_split(MfmaArgs a) {
 }
 
 template <int DT, int A>
-__global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WinOcc<DT, A>::W)))
+void k_mfma_win(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ float red[kMfmaWaves];
-    __shared__ int s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&a.counter[0], 1);
+    int id = blockIdx.x;
+    if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
+    const int ng = (a.ngroups + a.clip.wb - 1) / a.clip.wb;
+    const int tile = id / ng, grp = id - tile * ng;
+    process_tile_win<DT, A>(a, a.clip, tile, grp, lds, red);
+}
+
+// Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
+// (G = gridDim.x, every work-group resident) with no atomics; the host picks G
+// coprime with the number of block groups so that a work-group's tiles rotate
+// through the groups (whose K ranges differ).  The clip of tile t is the last
+// c with tile_prefix[c] <= t, searched in an LDS copy of the prefix table when
+// it fits.  ANY = 0 is the variant for batches whose clips all use WIN tiles
+// (compiled for the WIN register budget); ANY = 1 handles every layout.
+constexpr int kPrefixLds = 1024;
+
+template <int DT, int A, int ANY>
+__device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds, float* red, int* spre) {
+    const bool in_lds = a.nclips + 1 <= kPrefixLds;
+    if (in_lds) {
+        for (int i = threadIdx.x; i <= a.nclips; i += 256) spre[i] = a.tile_prefix[i];
         __syncthreads();
-        const int t = s_tile;
-        __syncthreads();
-        if (t >= a.total_tiles) break;
+    }
+    for (int t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
         int lo = 0, hi = a.nclips - 1;         // last clip c with tile_prefix[c] <= t
         while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (a.tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
+            const int mid = (lo + hi + 1) >> 1;
+            const int pm = in_lds ? spre[mid] : a.tile_prefix[mid];
+            if (pm <= t) lo = mid; else hi = mid - 1;
         }
-        const int local = t - a.tile_prefix[lo];
+        lo = __builtin_amdgcn_readfirstlane(lo);   // uniform: the descriptor stays scalar
+        const int local = t - (in_lds ? spre[lo] : a.tile_prefix[lo]);
         const ClipArg c = a.clips[lo];
-        if (c.mode == STAGE_LINEAR) {
+        if (!ANY || c.mode == STAGE_WIN) {
+            const int ng = (a.ngroups + c.wb - 1) / c.wb;
+            const int tile = local / ng, grp = local - tile * ng;
+            process_tile_win<DT, A>(a, c, tile, grp, lds, red);
+        } else if (c.mode == STAGE_LINEAR) {
             const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
             process_tile<DT, A>(a, c, tile, blk, lds, red);
         } else {
@@ -850,25 +981,42 @@ __global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
             const int tile = local / ng, grp = local - tile * ng;
             process_tile_split<DT>(a, c, tile, grp, lds, red);
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        int done = atomicAdd(&a.counter[1], 1);
-        if (done == (int)gridDim.x - 1) {      // last work-group out re-arms the counters
-            atomicExch(&a.counter[0], 0);
-            atomicExch(&a.counter[1], 0);
-        }
+        __syncthreads();                        // LDS free for the next tile
     }
 }
 
 template <int DT, int A>
+__global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ float red[kMfmaWaves];
+    __shared__ int spre[kPrefixLds];
+    persistent_body<DT, A, 1>(a, lds, red, spre);
+}
+
+template <int DT, int A>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WinOcc<DT, A>::W)))
+void k_mfma_persistent_win(MfmaArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ float red[kMfmaWaves];
+    __shared__ int spre[kPrefixLds];
+    persistent_body<DT, A, 0>(a, lds, red, spre);
+}
+
+// Dynamic LDS limit: a CU's 160 KiB less room for the static arrays (prefix
+// table, reductions).
+static int dyn_lds_max() { return mfma_max_lds_bytes() - 8192; }
+
+template <int DT, int A>
 static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
-    const size_t shm = 2 * (size_t)a.buf_bytes + (size_t)a.raw_bytes;
-    if (shm > (size_t)mfma_max_lds_bytes() - 1024) return hipErrorInvalidValue;
+    const size_t shm = (size_t)a.shm_bytes;
+    if (shm > (size_t)dyn_lds_max()) return hipErrorInvalidValue;
     (void)hipGetLastError();   // report only this launch's error
-    if (persistent)
+    if (persistent == 2)
+        hipLaunchKernelGGL((k_mfma_persistent_win<DT, A>), dim3(grid), dim3(256), shm, s, a);
+    else if (persistent)
         hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
+    else if (a.clip.mode == STAGE_WIN)
+        hipLaunchKernelGGL((k_mfma_win<DT, A>), dim3(grid), dim3(256), shm, s, a);
     else if (a.clip.mode == STAGE_ROWS)
         hipLaunchKernelGGL((k_mfma_split<DT>), dim3(grid), dim3(256), shm, s, a);
     else
@@ -878,9 +1026,10 @@ static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream
 
 template <int DT, int A>
 static hipError_t attrs2() {
-    const int lds = mfma_max_lds_bytes() - 1024;
-    const void* fns[3] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A>,
-                          (const void*)k_mfma_split<DT>};
+    const int lds = dyn_lds_max();
+    const void* fns[5] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A>,
+                          (const void*)k_mfma_split<DT>, (const void*)k_mfma_win<DT, A>,
+                          (const void*)k_mfma_persistent_win<DT, A>};
     for (const void* fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -926,7 +1075,8 @@ int mfma_max_lds_bytes() { return 160 * 1024; }
 template <int DT, int A>
 static int occ2(int persistent, size_t shm) {
     int n = 0;
-    const void* fn = persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_grid<DT, A>;
+    const void* fn = persistent == 2 ? (const void*)k_mfma_persistent_win<DT, A>
+                     : persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_win<DT, A>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, shm) != hipSuccess) return 1;
     return n;
 }

@@ -238,6 +238,15 @@ class Batch:
                "cwt_batch_execute")
         return outs
 
+    def prepare(self, plans, xs, outs=None) -> "PreparedBatch":
+        """Validate and marshal a batch once.  The returned object runs it again
+        (same plans and buffers) with a single library call per run."""
+        for x in xs:
+            _check_signal(x)
+        if outs is None:
+            outs = _outs_for(plans, xs)
+        return PreparedBatch(self, list(plans), list(xs), list(outs))
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             _lib.cwt_batch_destroy(self._h)
@@ -248,6 +257,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class PreparedBatch:
+    """A marshalled batch bound to its Batch context; keeps its tensors alive."""
+
+    def __init__(self, batch: Batch, plans, xs, outs):
+        self.batch = batch
+        self.plans, self.xs, self.outs = plans, xs, outs
+        self._n, self._P, self._X, self._L, self._O = _arrays(plans, xs, outs)
+
+    def run(self, stream=None, graph: bool = True):
+        _check(_lib.cwt_batch_execute(self.batch._h, self._P, self._X, self._L, self._O, self._n,
+                                      1 if graph else 0, _stream_ptr(stream)), "cwt_batch_execute")
+        return self.outs
 
 
 def raw():

@@ -190,6 +190,10 @@ EDGE = [
     ("hop 1000", 40000, [1.0, 64.0, 128.0], 1000),
     ("duplicates, unsorted", 4000, [9.0, 1.0, 9.0, 0.05, 3.0], 5),
     ("tile tail", 128 * 3 + 5, list(range(1, 9)), 1),
+    ("wide scale at hop 1 (chunked window)", 20000, [1.0, 300.0, 1024.0], 1),
+    ("wide scale at hop 3 (chunked window)", 20000, [2.0, 700.0], 3),
+    ("hop 2048 (row staging)", 40000, [1.0, 64.0, 512.0], 2048),
+    ("hop 5000, wide scale (row staging)", 60000, [1.0, 64.0, 1024.0], 5000),
 ]
 
 
@@ -322,6 +326,41 @@ def test_batch_bitwise_equals_single(torch, cw, dt):
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(alone, outs)):
         assert torch.equal(a, b), (dt, i, hs[i], xs[i].numel())
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_batch_mixed_layouts(torch, cw, dt):
+    """Whole-window, chunked-window and row-staged clips in one launch."""
+    scales = [1.0, 64.0, 1024.0]
+    plans = {h: cw.Plan(16000.0, scales, h, dt, signed=True) for h in (1, 64, 5000)}
+    xs, hs = _batch_inputs(torch, 21, 9, [1, 64, 5000], lo=3000, hi=30000)
+    pl = [plans[h] for h in hs]
+    alone = [p(x) for p, x in zip(pl, xs)]
+    for graph in (False, True):
+        outs = cw.Batch(16)(pl, xs, graph=graph)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(alone, outs)):
+            assert torch.equal(a, b), (dt, graph, i, hs[i])
+
+
+def test_prepared_batches_replay(torch, cw):
+    """Two marshalled batches run alternately through one context."""
+    scales = np.arange(1, 129)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (64, 256, 512)}
+    B = cw.Batch(48)
+    sets = []
+    for seed, count in ((31, 40), (32, 17)):
+        xs, hs = _batch_inputs(torch, seed, count, [64, 256, 512])
+        pl = [plans[h] for h in hs]
+        sets.append(([p(x) for p, x in zip(pl, xs)], B.prepare(pl, xs)))
+    for rep in range(3):
+        for j, (alone, prep) in enumerate(sets):
+            for o in prep.outs:
+                o.fill_(-1.0)
+            outs = prep.run(graph=True)
+            torch.cuda.synchronize()
+            for a, b in zip(alone, outs):
+                assert torch.equal(a, b), (rep, j)
 
 
 def test_batch_graph_replays(torch, cw):
