@@ -33,6 +33,30 @@ S = 128
 METRIC = "CWT coeffs/sec at hop 1 & 512, BF16-MFMA vs FP32 plain; serving p50/p99 ms"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
+
+# HBM bytes per launch of the two timed MFMA kernels, from two rocprofv3 --pmc
+# runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over
+# the dispatches of the leg), each scaled by what the counter reads for a plain
+# device copy of known size (FETCH_SCALE, WRITE_SCALE).  They describe the
+# kernel source whose SHA-256 is recorded and are reported only while it is
+# unchanged.
+FETCH_SCALE = 2.0
+WRITE_SCALE = 1.0
+TRAFFIC = {}
+
+
+def kernel_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_bytes(leg):
+    rec = TRAFFIC.get(leg)
+    if not rec or rec["src_sha256"] != kernel_sha():
+        return None
+    return 1024.0 * (FETCH_SCALE * rec["fetch_kib"] + WRITE_SCALE * rec["write_kib"])
 
 
 def log(*a):
@@ -51,6 +75,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["bf16-hop1", "fp32-hop1", "bf16-hop512", "fp32-hop512"], default=None,
                     help="time one leg only (for profiling runs)")
+    ap.add_argument("--hop-sweep", action="store_true",
+                    help="cost curve over hops 1, 2, 4, .., 1024 (one JSON line per hop) instead of the metric")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -82,6 +108,48 @@ def time_launches(torch, launch, nsets, steps, warmup):
     return t0.elapsed_time(t1), [a.elapsed_time(b) for a, b in ev]
 
 
+def hop_sweep(torch, cwth, synth, dev, scales, args):
+    """Cost of the transform of 10 s clips (128 scales) at hops 1, 2, 4, .., 1024:
+    BF16 MFMA (default configuration) and plain FP32, clips per launch growing
+    with the hop (min(hop, 256), one persistent launch) so each launch holds a
+    comparable amount of work; inputs resident, outputs rotated over two sets.
+    Reports coefficients/s, microseconds per clip, and the fraction of the
+    roof that binds at that hop (MFMA flops or HBM bytes, whichever takes
+    longer at peak)."""
+    fpc = alg_flops_per_coeff(scales)
+    flop_per_frame = float(fpc.sum())
+    base = [torch.from_numpy(synth.make_clip(synth.clip_seed(2, 40 + i), N, FS, float(np.linspace(-6, 6, 8)[i])))
+            .to(dev) for i in range(8)]
+    stream = torch.cuda.current_stream()
+    for hop in [1 << k for k in range(11)]:
+        nb = min(hop, 256)
+        K = -(-N // hop)
+        row = {"hop": hop, "clips_per_launch": nb, "frames_per_clip": K}
+        for dt in ("bf16", "fp32"):
+            plan = cwth.Plan(FS, scales, hop, dt)
+            B = cwth.Batch(nb)
+            sets = [[base[(j * 3 + k) % 8].clone() for k in range(nb)] for j in range(2)]
+            outs = [[torch.empty((S, K), dtype=torch.float32, device=dev) for _ in range(nb)] for _ in range(2)]
+            prep = [B.prepare([plan] * nb, sets[j], outs[j]) for j in range(2)]
+            steps = max(3, min(args.steps, 20 if dt == "bf16" else 5))
+            total, per = time_launches(torch, lambda s_: prep[s_ % 2].run(stream=stream.cuda_stream, graph=True), 2,
+                                       steps, min(args.warmup, 3))
+            ms = float(np.mean(per))
+            coeffs = nb * S * K
+            t_flop = flop_per_frame * K * nb / (PEAK_BF16_TFLOPS * 1e12 if dt == "bf16" else 157.3e12)
+            t_hbm = nb * (4.0 * N + 4.0 * S * K) / (PEAK_HBM_GBS * 1e9)
+            bound = "mfma" if dt == "bf16" and t_flop >= t_hbm else ("hbm" if t_hbm >= t_flop else "valu")
+            row[dt] = {"coeffs_per_s": coeffs / (ms * 1e-3), "us_per_clip": 1e3 * ms / nb, "ms_per_launch": ms,
+                       "config": plan.config, "bound": bound,
+                       "roof_frac": max(t_flop, t_hbm) / (ms * 1e-3)}
+            del prep, sets, outs, B, plan
+        row["ratio_bf16_over_fp32"] = row["bf16"]["coeffs_per_s"] / row["fp32"]["coeffs_per_s"]
+        print(json.dumps({"metric": "hop sweep: " + METRIC, **row}), flush=True)
+        log("hop %4d: bf16 %.3e coeffs/s (%.1f us/clip, %.2f of %s roof), fp32 %.3e, ratio %.1f" % (
+            hop, row["bf16"]["coeffs_per_s"], row["bf16"]["us_per_clip"], row["bf16"]["roof_frac"],
+            row["bf16"]["bound"], row["fp32"]["coeffs_per_s"], row["ratio_bf16_over_fp32"]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,6 +176,9 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": 5}))
         return
     scales = synth.linear_scales(S)
+    if args.hop_sweep:
+        hop_sweep(torch, cwth, synth, dev, scales, args)
+        return
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame
 
@@ -157,7 +228,7 @@ def main():
         ms = total / steps
         coeffs = nb * S * K512
         return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": float(np.mean(per)),
-                "clips_per_launch": nb, "steps": steps}
+                "clips_per_launch": nb, "steps": steps, "config": plan.config}
 
     legs = [("bf16", 1), ("fp32", 1), ("bf16", 512), ("fp32", 512)]
     if args.only:
@@ -202,8 +273,9 @@ def main():
         flops = flops_per_frame * K1                      # one launch = one clip
         ach = flops / (r["per_launch_ms"] * 1e-3) / 1e12
         line["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                            "frac": ach / PEAK_BF16_TFLOPS, "traffic": None,
-                            "kernel": "k_mfma_grid<bf16> hop 1, one 160000-sample clip x 128 scales",
+                            "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic_bytes("bf16_hop1"),
+                            "kernel": "k_mfma_win<bf16> (configuration %d), hop 1, one 160000-sample clip x 128 "
+                                      "scales per launch" % r["config"],
                             "alg_flop_per_launch": flops, "avg_launch_ms": r["per_launch_ms"]}
     if ("bf16", 512) in result:
         r = result[("bf16", 512)]
@@ -211,7 +283,9 @@ def main():
         gbs = byt / (r["per_launch_ms"] * 1e-3) / 1e9
         line["roofline_hop512"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                    "frac": gbs / PEAK_HBM_GBS, "alg_bytes_per_launch": byt,
-                                   "kernel": "k_mfma_persistent<bf16> hop 512, %d clips" % nb}
+                                   "traffic": traffic_bytes("bf16_hop512"), "avg_launch_ms": r["per_launch_ms"],
+                                   "kernel": "k_mfma_persistent_win<bf16> (configuration %d), hop 512, %d clips "
+                                             "per launch" % (r["config"], nb)}
 
     # ---------------- serving ----------------
     if not args.no_serve and not args.only:

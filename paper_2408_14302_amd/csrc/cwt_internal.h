@@ -66,6 +66,8 @@ struct ClipArg {
     int32_t copies;  // shifted copies (linear mode)
     int32_t swz;     // XOR-swizzle shift (linear and window modes), -1 for none
     int32_t wb;      // window mode: 32-scale blocks per work-group (1, 2 or 4)
+    int32_t cso;     // linear and window modes with copies > 1: copy stride = units + cso (16-byte units)
+    int32_t ws;      // window mode: waves sharing one frame group (their blocks split WS ways)
 };
 
 // LINEAR: chunked linear window, one block per tile; ROWS: chunked per-frame
@@ -107,7 +109,8 @@ struct DirectArgs {
 hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
 hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, const int32_t* d_prefix,
                                int nclips, int total_tiles, hipStream_t s);
-// A = 32-frame blocks per wave (1, 2, 4); the third argument is unused.
+// A = 32-frame blocks per wave (1, 2, 4; 8 for WIN tiles of BF16/FP16); the
+// third argument is unused.
 // persistent: 0 = one grid tile per work-group (single clip), 1 = persistent
 // batch kernel for any layout, 2 = persistent batch kernel for WIN tiles only.
 hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,

@@ -86,24 +86,31 @@ static cwt_status current_device(int* dev, DeviceInfo* info) {
 }
 
 // ---------------------------------------------------------------------------
-// Kernel configurations.  MFMA: A = 32-frame blocks per wave, wb = preferred
-// 32-scale blocks per work-group for WIN tiles (tile = 32*A*(4/wb) frames),
-// chunk = upper bound of the K-steps per LDS buffer of chunked LINEAR tiles
-// (a multiple of 8; pick_chunk() shrinks it to what the LDS budget holds).
+// Kernel configurations.  MFMA: A = 32-frame blocks per wave; wb = preferred
+// 32-scale blocks per work-group and ws = waves that share one frame group
+// (each running wb/ws of the blocks in turn) for WIN tiles of 32*A*(4/ws)
+// frames; chunk = upper bound of the K-steps per LDS buffer of chunked LINEAR
+// tiles (a multiple of 8; pick_chunk() shrinks it to what the LDS budget holds).
 struct MfmaCfg {
     int A;
     int wb;
+    int ws;
     int chunk;
 };
 static const MfmaCfg kMfmaCfgs[] = {
-    {4, 1, 32},   // 0: 512 frames x 1 block
-    {2, 1, 64},   // 1: 256 frames x 1 block
-    {1, 1, 64},   // 2: 128 frames x 1 block
-    {4, 4, 32},   // 3: 128 frames x 4 blocks
-    {2, 4, 64},   // 4:  64 frames x 4 blocks
-    {1, 4, 64},   // 5:  32 frames x 4 blocks
-    {2, 2, 64},   // 6: 128 frames x 2 blocks
-    {4, 2, 32},   // 7: 256 frames x 2 blocks
+    {4, 4, 1, 32},   // 0: 512 frames, every wave runs all 4 blocks
+    {4, 4, 2, 32},   // 1: 256 frames, blocks {0,3} / {1,2} per wave
+    {2, 4, 1, 64},   // 2: 256 frames, every wave runs all 4 blocks
+    {4, 4, 4, 32},   // 3: 128 frames, one block per wave
+    {2, 4, 4, 64},   // 4:  64 frames, one block per wave
+    {1, 4, 4, 64},   // 5:  32 frames, one block per wave
+    {2, 4, 2, 64},   // 6: 128 frames, blocks {0,3} / {1,2} per wave
+    {1, 4, 2, 64},   // 7:  64 frames, blocks {0,3} / {1,2} per wave
+    {1, 4, 1, 64},   // 8: 128 frames, every wave runs all 4 blocks
+    {4, 1, 1, 32},   // 9: 512 frames x 1 block
+    {8, 4, 4, 32},   // 10: 256 frames, one block per wave (WIN only, BF16/FP16)
+    {8, 4, 2, 32},   // 11: 512 frames, blocks {0,3} / {1,2} per wave (WIN only, BF16/FP16)
+    {8, 4, 1, 32},   // 12: 1024 frames, every wave runs all 4 blocks (WIN only, BF16/FP16)
 };
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 static const int kFp8Cfg = 5;   // the one FP8 configuration (see cfg_fits)
@@ -122,13 +129,30 @@ static int64_t gcd64(int64_t a, int64_t b) {
 
 // Staging geometry of one clip for the MFMA kernel; mirrors make_geo() in mfma.hip.
 struct Staging {
-    int mode, copies, swz;
+    int mode, copies, swz, cso;
     int64_t bytes;      // one LDS operand buffer (all planes); two are used
     int64_t raw_bytes;  // LINEAR: the raw FP32 window buffer
 };
 
 static const int64_t kLdsBudget = 52 * 1024;   // chunked tiles: three work-groups per CU
 static const int64_t kWinBudget = 80 * 1024;   // WIN tiles: at least two work-groups per CU
+
+// Extra 16-byte units between the shifted copies of a linear window, by hop
+// mod 128 (copies > 1 only).  The X-fragment reads of a wave hit lane
+// addresses (p % U / gh) * stride + p / U, p = frame * hop + 8 * half; this
+// offset maximises their measured LDS b128 read rate on MI355X (2-byte
+// operands; e.g. hop 1: 168 B/clk/CU at offset 4 against 110 at offset 2).
+// FP8 windows (16 elements per unit) keep 16 / copies.
+static const int8_t kCopyStrideOffset[128] = {
+     0,  4,  4,  6,  8,  1,  2,  0,  0,  3,  3,  3,  7,  1,  1,  0,
+     0,  2,  2,  0,  6,  4,  0,  1,  0,  1,  1,  0,  5,  0,  0,  0,
+     0,  0,  0,  2,  4, 10,  0,  1,  0,  7,  7,  7,  3,  6,  2,  0,
+     0,  6,  6,  4,  2,  0,  0,  1,  0,  5,  5,  1,  1,  3,  0,  1,
+     0,  4,  4,  1,  0,  6,  1,  3,  0,  3,  3,  0, 15,  2,  2,  1,
+     0,  2,  2,  7, 14, 12,  3,  5,  0,  1,  1, 20, 13,  0,  0,  0,
+     0,  0,  0,  2, 12, 11,  1,  1,  0,  7,  7,  2, 11, 22,  2,  0,
+     0,  6,  6,  1, 10,  8,  5,  6,  0,  5,  5,  1,  9,  4, 14, 15,
+};
 
 // The LINEAR layout for F frames and `chunk` K-steps.
 static Staging linear_staging(int dt, int hop, int F, int chunk) {
@@ -137,9 +161,10 @@ static Staging linear_staging(int dt, int hop, int F, int chunk) {
     s.mode = STAGE_LINEAR;
     const int gh = (int)gcd64(hop, U);
     s.copies = U / gh;
+    s.cso = s.copies == 1 ? 0 : dt == DT_FP8 ? 16 / s.copies : kCopyStrideOffset[hop % 128];
     const int64_t pmax = (int64_t)(F - 1) * hop + (int64_t)KS * chunk - 1;
     const int64_t len_u = ((pmax / U + 1) + 15) & ~int64_t(15);
-    const int64_t cs = len_u + (s.copies > 1 ? 16 / s.copies : 0);
+    const int64_t cs = len_u + s.cso;
     s.bytes = (int64_t)s.copies * cs * 16 * P;
     s.raw_bytes = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;   // raw_floats() in mfma.hip
     s.swz = -1;
@@ -159,6 +184,7 @@ static Staging split_staging(int dt, int F, int chunk) {
     s.mode = STAGE_ROWS;
     s.copies = 1;
     s.swz = -1;
+    s.cso = 0;
     s.bytes = (int64_t)F * (KS * chunk / U + 1) * 16 * P;
     s.raw_bytes = 0;
     return s;
@@ -372,6 +398,7 @@ static cwt_status acquire_bank(int dt, int device, const std::vector<double>& sc
 struct ClipLayout {
     Staging s;
     int wb = 1;          // scale blocks per work-group
+    int ws = 1;          // WIN: waves sharing a frame group
     int F = 0;           // frames per tile
     int64_t groups = 0;  // work-group tiles per frame tile
 };
@@ -438,24 +465,29 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
 }
 
 // Default configuration by hop (measured on MI355X, 128 linear scales, 10 s
-// clips): every hop does best with one window shared by four scale blocks;
-// the frame tile narrows as the hop grows (128 frames at hop <= 2, 64 up to
-// hop 8, 32 beyond).  FP8 has one configuration.
+// clips): small hops share a 128-frame window between two pairs of waves,
+// each running a balanced pair of blocks ({0,3}, {1,2}); larger hops take
+// narrower frame tiles with one block per wave.  FP8 has one configuration.
 static int default_cfg(int dt, int hop) {
     if (dt == DT_FP32) return 0;
     if (dt == DT_FP8) return kFp8Cfg;
-    if (hop <= 2) return 3;
+    if (hop <= 4) return 6;
     if (hop <= 8) return 4;
     return 5;
 }
 
+static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c, int chunk);
+
 static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
-    (void)hop;
     if (p->dt == DT_FP32) return cfg == 0;
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
     // FP8 scales the signal per tile; one fixed tile geometry keeps every
     // clip's result independent of the configuration and of its batch.
     if (p->dt == DT_FP8) return cfg == kFp8Cfg;
+    const MfmaCfg& c = kMfmaCfgs[cfg];
+    if (c.A == 8)   // WIN tiles of the 2-byte types only
+        return (p->dt == DT_BF16 || p->dt == DT_FP16) &&
+               clip_layout(p->dt, *p->bank, hop, c, c.chunk).s.mode == STAGE_WIN;
     return true;   // a layout always exists: WIN, chunked LINEAR or SPLIT tiles
 }
 
@@ -467,13 +499,15 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
     ClipLayout L;
     const int nblk = (int)bk.blocks.size(), cap = wb_cap(nblk);
     for (int wb = std::min(c.wb, cap); wb <= cap; wb *= 2) {
-        const int F = 32 * c.A * (4 / wb);
+        const int ws = std::min(c.ws, wb);
+        const int F = 32 * c.A * (4 / ws);
         Staging s = linear_staging(dt, hop, F, bk.win_steps[log2_small(wb)]);
         if (s.bytes <= kWinBudget) {
             s.mode = STAGE_WIN;
             s.raw_bytes = 0;
             L.s = s;
             L.wb = wb;
+            L.ws = ws;
             L.F = F;
             L.groups = (nblk + wb - 1) / wb;
             return L;
@@ -514,8 +548,8 @@ static void set_cfg(cwt_plan_s* p, int cfg) {
 // Launch of one clip.
 // One clip's kernel record and, for the MFMA path, its layout (*lay) and its
 // work-group tiles (*tiles_out: frame tiles x block groups).
-static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, int cfg, int chunk,
-                         ClipLayout* lay, int64_t* tiles_out) {
+static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float* out, const MfmaCfg& mc,
+                         bool cached_ok, int chunk, ClipLayout* lay, int64_t* tiles_out) {
     ClipArg c;
     std::memset(&c, 0, sizeof(c));
     c.x = x;
@@ -524,18 +558,21 @@ static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float
     c.hop = p->hop;
     c.K = (len + p->hop - 1) / p->hop;
     c.wb = 1;
+    c.ws = 1;
     if (p->dt == DT_FP32) {
         c.ntile = (int32_t)((c.K + kDirectFrames - 1) / kDirectFrames);
         if (tiles_out) *tiles_out = (int64_t)c.ntile * (((int64_t)p->bank->dgroups.size() + kDirectWaves - 1) / kDirectWaves);
         return c;
     }
-    const bool cached = cfg == p->cfg && (p->lay.s.mode != STAGE_LINEAR || chunk == p->lay_chunk);
-    const ClipLayout L = cached ? p->lay : clip_layout(p->dt, *p->bank, p->hop, kMfmaCfgs[cfg], chunk);
+    const bool cached = cached_ok && (p->lay.s.mode != STAGE_LINEAR || chunk == p->lay_chunk);
+    const ClipLayout L = cached ? p->lay : clip_layout(p->dt, *p->bank, p->hop, mc, chunk);
     c.ntile = (int32_t)((c.K + L.F - 1) / L.F);
     c.mode = L.s.mode;
     c.copies = L.s.copies;
     c.swz = L.s.swz;
+    c.cso = L.s.cso;
     c.wb = L.wb;
+    c.ws = L.ws;
     if (lay) *lay = L;
     if (tiles_out) *tiles_out = (int64_t)c.ntile * L.groups;
     return c;
@@ -552,7 +589,7 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
         a.groups = bk.d_dgroups;
         a.ngroups = (int)bk.dgroups.size();
         a.signed_out = p->signed_out;
-        a.clip = make_clip(p, x, len, out, 0, 8, nullptr, &tiles);
+        a.clip = make_clip(p, x, len, out, kMfmaCfgs[0], false, 8, nullptr, &tiles);
         a.xcd_remap = 1;
         HIP_TRY(launch_direct(a, stream), "direct launch");
         return CWT_OK;
@@ -571,7 +608,7 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
     a.split_wb = sg.wb;
     a.split_chunk = sg.chunk;
     ClipLayout L;
-    a.clip = make_clip(p, x, len, out, cfg, chunk, &L, &tiles);
+    a.clip = make_clip(p, x, len, out, c, cfg == p->cfg, chunk, &L, &tiles);
     a.buf_bytes = L.s.mode == STAGE_WIN ? 0 : (int32_t)L.s.bytes;
     a.raw_bytes = (int32_t)L.s.raw_bytes;
     a.shm_bytes = (int32_t)layout_lds(L);
@@ -601,7 +638,15 @@ struct cwt_batch_s {
     hipEvent_t done[2] = {nullptr, nullptr};
     bool used[2] = {false, false};
     int flip = 0;
-    uint8_t* d_desc = nullptr;
+    // Two device descriptor buffers; shadow[i] is what d_desc[i] holds (or will
+    // hold once its upload has run), ddone[i] completes after the last launch
+    // that read it.
+    uint8_t* d_desc[2] = {nullptr, nullptr};
+    std::vector<uint8_t> shadow[2];
+    hipEvent_t ddone[2] = {nullptr, nullptr};
+    hipStream_t dstream[2] = {nullptr, nullptr};
+    bool dused[2] = {false, false};
+    int dnext = 0;
     hipStream_t cap_stream = nullptr;
     std::map<std::tuple<int, int, int, int, int, int>, GraphEntry> graphs;
     std::mutex mu;
@@ -618,7 +663,13 @@ struct cwt_batch_s {
             if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
             if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
         }
-        if (d_desc) (void)hipFree(d_desc);
+        for (int i = 0; i < 2; ++i) {
+            if (ddone[i]) {
+                (void)hipEventSynchronize(ddone[i]);
+                (void)hipEventDestroy(ddone[i]);
+            }
+            if (d_desc[i]) (void)hipFree(d_desc[i]);
+        }
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
@@ -639,7 +690,10 @@ static cwt_status batch_init(cwt_batch_s* b, int max_clips) {
         HIP_TRY(hipHostMalloc((void**)&b->pinned[i], b->desc_cap, hipHostMallocDefault), "pinned descriptors");
         HIP_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming), "batch event");
     }
-    HIP_TRY(hipMalloc(&b->d_desc, b->desc_cap), "device descriptors");
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(hipMalloc(&b->d_desc[i], b->desc_cap), "device descriptors");
+        HIP_TRY(hipEventCreateWithFlags(&b->ddone[i], hipEventDisableTiming), "descriptor event");
+    }
     HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "capture stream");
     HIP_TRY(hipDeviceSynchronize(), "batch init");
     return CWT_OK;
@@ -686,15 +740,25 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     // clips have a fixed geometry per (bank, hop, configuration).
     const bool fp32 = p0->dt == DT_FP32;
     const int cfg = p0->cfg;
-    const MfmaCfg c = kMfmaCfgs[fp32 ? 0 : cfg];
+    MfmaCfg c = kMfmaCfgs[fp32 ? 0 : cfg];
+    bool cached_ok = true;   // plans[i]->lay is valid for this launch when plans[i]->cfg == cfg
     int chunk = 8;
-    bool any_linear = false;
+    bool any_linear = false, all_win = true;
     for (int i = 0; i < n && !fp32; ++i)
         if (lens[i] > 0) {
             const ClipLayout& L = plans[i]->cfg == cfg ? plans[i]->lay
                                   : clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk);
             any_linear = any_linear || L.s.mode == STAGE_LINEAR;
+            all_win = all_win && L.s.mode == STAGE_WIN;
         }
+    if (c.A == 8 && !all_win) {
+        // 256-frame waves exist for WIN tiles only: run this batch with A = 4
+        c.A = 4;
+        cached_ok = false;
+        any_linear = false;
+        for (int i = 0; i < n; ++i)
+            if (lens[i] > 0) any_linear = any_linear || clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk).s.mode == STAGE_LINEAR;
+    }
     if (any_linear) {
         for (int ch = c.chunk; ch >= 8; ch -= 8) {
             int64_t mb = 0, mr = 0;
@@ -727,7 +791,8 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     int64_t maxbuf = 16, maxraw = 0, maxwin = 0;
     for (int i : order) {
         ClipLayout L;
-        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], fp32 ? 0 : cfg, chunk, &L, &ctiles[i]);
+        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], c, cached_ok && plans[i]->cfg == cfg, chunk, &L,
+                             &ctiles[i]);
         if (fp32) continue;
         if (L.s.mode == STAGE_WIN) {
             maxwin = std::max(maxwin, L.s.bytes);
@@ -753,6 +818,31 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     ((int32_t*)host)[1] = (int32_t)total;
     const size_t used_bytes = 16 + sizeof(ClipArg) * nc + sizeof(int32_t) * (nc + 1);
 
+    // Device descriptors: reuse the buffer that already holds exactly these
+    // (a prepared batch run again: no upload); otherwise overwrite the other
+    // one once the launches that read it have completed.
+    int ds = -1;
+    for (int i = 0; i < 2; ++i)
+        if (b->shadow[i].size() == used_bytes && std::memcmp(b->shadow[i].data(), host, used_bytes) == 0) ds = i;
+    const bool upload = ds < 0;
+    if (upload) {
+        ds = b->dnext;
+        b->dnext ^= 1;
+        if (b->dused[ds]) HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor reuse wait");
+        b->shadow[ds].assign(host, host + used_bytes);
+    } else if (b->dused[ds] && b->dstream[ds] != stream) {
+        HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
+    }
+    uint8_t* const dd = b->d_desc[ds];
+    auto finish = [&]() -> cwt_status {
+        HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
+        HIP_TRY(hipEventRecord(b->ddone[ds], stream), "descriptor event");
+        b->used[slot] = true;
+        b->dused[ds] = true;
+        b->dstream[ds] = stream;
+        return CWT_OK;
+    };
+
     if (fp32) {
         // The plain path: descriptor upload and one flat launch over every tile.
         DirectArgs d;
@@ -761,13 +851,10 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         d.groups = bk.d_dgroups;
         d.ngroups = (int)bk.dgroups.size();
         d.signed_out = p0->signed_out;
-        HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
-        HIP_TRY(launch_direct_batch(d, (const ClipArg*)(b->d_desc + 16),
-                                    (const int32_t*)(b->d_desc + 16 + sizeof(ClipArg) * nc), nc, (int)total,
-                                    stream), "direct batch launch");
-        HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
-        b->used[slot] = true;
-        return CWT_OK;
+        if (upload) HIP_TRY(hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
+        HIP_TRY(launch_direct_batch(d, (const ClipArg*)(dd + 16), (const int32_t*)(dd + 16 + sizeof(ClipArg) * nc), nc,
+                                    (int)total, stream), "direct batch launch");
+        return finish();
     }
     MfmaArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -784,14 +871,14 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     a.shm_bytes = (int32_t)std::max(2 * maxbuf + maxraw, maxwin);
     a.xcd_remap = 0;
     // The descriptor pointers are fixed device addresses; counts live in the header.
-    a.clips = (const ClipArg*)(b->d_desc + 16);
-    a.tile_prefix = (const int32_t*)(b->d_desc + 16 + sizeof(ClipArg) * nc);
+    a.clips = (const ClipArg*)(dd + 16);
+    a.tile_prefix = (const int32_t*)(dd + 16 + sizeof(ClipArg) * nc);
     a.nclips = nc;
     a.total_tiles = (int32_t)total;
     // WIN-only batches run the kernel compiled for the WIN register budget.
-    bool all_win = true;
-    for (int j = 0; j < nc; ++j) all_win = all_win && hc[j].mode == STAGE_WIN;
-    const int pkind = all_win ? 2 : 1;
+    bool win_only = true;
+    for (int j = 0; j < nc; ++j) win_only = win_only && hc[j].mode == STAGE_WIN;
+    const int pkind = win_only ? 2 : 1;
     int64_t groups_lcm = 1;
     for (int j = 0; j < nc; ++j) {
         const int64_t ng = hc[j].mode == STAGE_WIN ? (a.ngroups + hc[j].wb - 1) / hc[j].wb
@@ -803,17 +890,19 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
                                             total);
 
     if (!use_graph) {
-        HIP_TRY(hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
+        if (upload) HIP_TRY(hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
         HIP_TRY(launch_mfma(p0->dt, c.A, 1, a, pkind, grid, stream), "persistent launch");
     } else {
-        // One graph per (shape, pinned buffer): the descriptor copy's source is
-        // then fixed, and its size and the kernel arguments (counts, chunk)
-        // are refreshed only when they differ from the previous replay.
-        auto key = std::make_tuple(p0->dt, c.A, (int)a.shm_bytes, grid, pkind, slot);
+        // One graph per (shape, pinned buffer, device buffer, with or without
+        // the upload): the copy's source and destination are then fixed, and
+        // its size and the kernel arguments (counts, chunk) are refreshed only
+        // when they differ from the previous replay.
+        auto key = std::make_tuple(p0->dt, c.A, (int)a.shm_bytes, grid, pkind, 4 * slot + 2 * ds + (upload ? 1 : 0));
         GraphEntry& ge = b->graphs[key];
         if (!ge.exec) {
             HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-            hipError_t e1 = hipMemcpyAsync(b->d_desc, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream);
+            hipError_t e1 = upload ? hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream)
+                                   : hipSuccess;
             hipError_t e2 = launch_mfma(p0->dt, c.A, 1, a, pkind, grid, b->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e3 = hipStreamEndCapture(b->cap_stream, &g);
@@ -833,13 +922,13 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
                 if (t == hipGraphNodeTypeMemcpy) ge.copy_node = nd;
                 if (t == hipGraphNodeTypeKernel) ge.kernel_node = nd;
             }
-            if (!ge.copy_node || !ge.kernel_node) return fail(CWT_ERR_INTERNAL, "unexpected graph shape");
+            if ((upload && !ge.copy_node) || !ge.kernel_node) return fail(CWT_ERR_INTERNAL, "unexpected graph shape");
             HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0), "graph instantiate");
             std::memcpy(&ge.args, &a, sizeof(a));   // padding included, for the memcmp below
             ge.copy_bytes = used_bytes;
         } else {
-            if (ge.copy_bytes != used_bytes) {
-                HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, b->d_desc, host, used_bytes,
+            if (upload && ge.copy_bytes != used_bytes) {
+                HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, dd, host, used_bytes,
                                                           hipMemcpyHostToDevice), "graph copy update");
                 ge.copy_bytes = used_bytes;
             }
@@ -855,9 +944,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         }
         HIP_TRY(hipGraphLaunch(ge.exec, stream), "graph launch");
     }
-    HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
-    b->used[slot] = true;
-    return CWT_OK;
+    return finish();
 }
 
 // Implicit batch contexts, one per (thread, device, stream).

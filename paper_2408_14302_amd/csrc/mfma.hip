@@ -98,7 +98,7 @@ __device__ __forceinline__ Geo make_geo(const ClipArg& c, int F, int chunk) {
     if (g.mode != STAGE_ROWS) {
         int pmax = (F - 1) * c.hop + T::KS * chunk - 1;
         g.len_u = ((pmax / T::U + 1) + 15) & ~15;
-        g.cs = g.len_u + (g.copies > 1 ? 16 / g.copies : 0);
+        g.cs = g.len_u + (g.copies > 1 ? c.cso : 0);
         g.rs = 0;
         g.plane_bytes = g.copies * g.cs * 16;
     } else {
@@ -502,32 +502,29 @@ enum LoopMode : int { LM_LINEAR = 0, LM_LINEAR_SWZ = 1, LM_ROWS = 2 };
 
 // Signal fragments of step d (relative to the chunk's first step) for the
 // lane's A frame blocks.  `vb[fa]` is the lane's byte offset of step 0.
-template <int DT, int A, int LM>
-__device__ __forceinline__ void load_x(const uint8_t* lds, int plane_bytes, int swz, const int (&vb)[A],
-                                       const int (&unit0)[A], int d, Frag<DT> (&x)[A]) {
+template <int DT, int LM>
+__device__ __forceinline__ void load_x1(const uint8_t* lds, int plane_bytes, int swz, int vb, int unit0, int d,
+                                        Frag<DT>& x) {
     using T = Tr<DT>;
 #pragma unroll
-    for (int fa = 0; fa < A; ++fa) {
-#pragma unroll
-        for (int u = 0; u < T::LU; ++u) {
-            int off;
-            if constexpr (LM == LM_LINEAR_SWZ) {
-                const int unit = unit0[fa] + d * (T::KS / T::U) + u;
-                off = vb[fa] + ((unit ^ ((unit >> swz) & 15)) << 4);
-            } else {
-                off = vb[fa] + ((d * (T::KS / T::U) + u) << 4);
-            }
-#pragma unroll
-            for (int p = 0; p < T::PLANES; ++p)
-                x[fa].u[p][u] = *(const i32x4*)(lds + p * plane_bytes + off);
+    for (int u = 0; u < T::LU; ++u) {
+        int off;
+        if constexpr (LM == LM_LINEAR_SWZ) {
+            const int unit = unit0 + d * (T::KS / T::U) + u;
+            off = vb + ((unit ^ ((unit >> swz) & 15)) << 4);
+        } else {
+            off = vb + ((d * (T::KS / T::U) + u) << 4);
         }
+#pragma unroll
+        for (int p = 0; p < T::PLANES; ++p) x.u[p][u] = *(const i32x4*)(lds + p * plane_bytes + off);
     }
 }
 
-template <int DT, int A>
-__device__ __forceinline__ void mma_frags(const Frag<DT>& t, const Frag<DT> (&x)[A], f32x16 (&acc)[A]) {
+template <int DT, int A, int LM>
+__device__ __forceinline__ void load_x(const uint8_t* lds, int plane_bytes, int swz, const int (&vb)[A],
+                                       const int (&unit0)[A], int d, Frag<DT> (&x)[A]) {
 #pragma unroll
-    for (int fa = 0; fa < A; ++fa) acc[fa] = mma_all<DT>(t, x[fa], acc[fa]);
+    for (int fa = 0; fa < A; ++fa) load_x1<DT, LM>(lds, plane_bytes, swz, vb[fa], unit0[fa], d, x[fa]);
 }
 
 // Per-lane LDS byte offset of step 0 of a chunk (within one buffer) and, for
@@ -553,37 +550,77 @@ __device__ __forceinline__ void lane_bases(const ClipArg& c, const Geo& g, int f
     }
 }
 
+// Instruction order of one K-step, fixed for the scheduler: for each frame
+// block, its MFMA(s) and then the read of its next signal fragment into the
+// registers the MFMA has just consumed; last the tap load eight steps ahead.
+// Each signal read then has the other A - 1 frame blocks' MFMAs to land.
+// Without the order the reads sink next to the MFMAs that consume them.
+template <int DT, int A, bool NEXT>
+__device__ __forceinline__ void sched_step() {
+    using T = Tr<DT>;
+    constexpr int NX = T::LU * T::PLANES;            // ds_read_b128 per frame block
+    constexpr int NM = DT == DT_BF16X3 ? 3 : 1;      // MFMAs per frame block
+    constexpr int NT = T::LU * T::PLANES;            // tap loads per step
+#pragma unroll
+    for (int fa = 0; fa < A; ++fa) {
+        __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);                        // MFMA
+        if constexpr (NEXT) __builtin_amdgcn_sched_group_barrier(0x100, NX, 0);   // DS read
+    }
+    __builtin_amdgcn_sched_group_barrier(0x020, NT, 0);                            // VMEM read
+}
+
+// Signal fragments in flight per frame block: with few frame blocks per wave
+// a fragment read right after its MFMA would be needed again only A MFMAs
+// later, too soon for LDS, so small A reads two steps ahead.
+template <int A>
+constexpr int x_depth() { return A >= 4 ? 1 : 2; }
+
+// Eight K-steps starting q steps into the range.  Tap fragments (from L2) are
+// loaded eight steps ahead into two banks of four register sets; each frame
+// block's signal fragment (from LDS) for step j + XD is read into the
+// registers that step j's MFMA has just consumed.  Every register slot is a
+// compile-time constant.  LAST: the final group (no reads past its end).
+template <int DT, int A, int LM, int XD, bool LAST>
+__device__ __forceinline__ void step_group(const uint8_t* cur, const Geo& g, int swz, const int (&base)[A],
+                                           const int (&unit0)[A], int dq, int s8, int hi, int lo,
+                                           const uint8_t* __restrict__ tbase, Frag<DT> (&ta)[4], Frag<DT> (&tb)[4],
+                                           Frag<DT> (&x)[XD][A], f32x16 (&acc)[A]) {
+    using T = Tr<DT>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        Frag<DT>& tcur = j < 4 ? ta[j & 3] : tb[j & 3];
+        const bool next = !(LAST && j + XD > 7);
+#pragma unroll
+        for (int fa = 0; fa < A; ++fa) {
+            acc[fa] = mma_all<DT>(tcur, x[j % XD][fa], acc[fa]);
+            if (next) load_x1<DT, LM>(cur, g.plane_bytes, swz, base[fa], unit0[fa], dq + j + XD, x[j % XD][fa]);
+        }
+        load_tap<DT>(tbase + (int64_t)(min(s8 + 8 + j, hi) - lo) * T::STEP, lane, tcur);
+        if (next)
+            sched_step<DT, A, true>();
+        else
+            sched_step<DT, A, false>();
+    }
+}
+
 // The MFMAs of steps ks_c+d0 .. ks_c+d0+ns-1 (ns a multiple of 8) of the chunk
-// starting at ks_c, from LDS buffer `cur`.  Tap fragments (from L2) are loaded
-// eight steps ahead into two banks of four register sets, signal fragments
-// (from LDS) one step ahead into a ring of two; every slot is a compile-time
-// constant.
+// starting at ks_c, from LDS buffer `cur`; ta/tb hold the taps of the first
+// eight steps on entry.
 template <int DT, int A, int LM>
 __device__ __forceinline__ void compute_chunk(const uint8_t* cur, const Geo& g, int swz, const int (&base)[A],
                                               const int (&unit0)[A], int ks_c, int d0, int ns, int hi, int lo,
                                               const uint8_t* __restrict__ tbase, Frag<DT> (&ta)[4],
                                               Frag<DT> (&tb)[4], f32x16 (&acc)[A]) {
-    using T = Tr<DT>;
-    const int lane = threadIdx.x & 63;
-    auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
-    Frag<DT> x0[A], x1[A];
-    load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0, x0);
-    for (int q = 0; q < ns; q += 8) {
-        const int s8 = ks_c + d0 + q;
-        const bool last = q + 8 >= ns;
+    constexpr int XD = x_depth<A>();
+    Frag<DT> x[XD][A];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            Frag<DT>& tcur = j < 4 ? ta[j & 3] : tb[j & 3];
-            if ((j & 1) == 0) {
-                if (j < 7) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0 + q + j + 1, x1);
-                mma_frags<DT, A>(tcur, x0, acc);
-            } else {
-                if (j < 7 || !last) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0 + q + j + 1, x0);
-                mma_frags<DT, A>(tcur, x1, acc);
-            }
-            load_tap<DT>(tap(s8 + 8 + j), lane, tcur);
-        }
-    }
+    for (int d = 0; d < XD; ++d) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0 + d, x[d]);
+    int q = 0;
+    for (; q + 8 < ns; q += 8)
+        step_group<DT, A, LM, XD, false>(cur, g, swz, base, unit0, d0 + q, ks_c + d0 + q, hi, lo, tbase, ta, tb, x,
+                                         acc);
+    step_group<DT, A, LM, XD, true>(cur, g, swz, base, unit0, d0 + q, ks_c + d0 + q, hi, lo, tbase, ta, tb, x, acc);
 }
 
 // LINEAR layouts: raw window by direct loads, converted between chunks.
@@ -768,7 +805,7 @@ __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c
 template <int DT, int A>
 struct WinOcc {
     static constexpr bool wide = DT == DT_BF16X3 || DT == DT_FP8;
-    static constexpr int W = wide ? (A == 4 ? 1 : 2) : (A == 4 ? 3 : 4);
+    static constexpr int W = wide ? (A >= 4 ? 1 : 2) : (A >= 8 ? 2 : (A >= 2 ? 3 : 4));
     static constexpr int SF = 32;
 };
 
@@ -824,50 +861,35 @@ __device__ __forceinline__ void win_stage(const ClipArg& c, const Geo& g, int64_
     }
 }
 
-// WIN tile: F = 32*A*(4/WB) consecutive frames against the WB consecutive
-// 32-scale blocks of group grp.  Wave w takes block slot (w + tile) % WB of
-// the group (rotated so that the widest block does not always land on the
-// same SIMD) and the A frame blocks A*(w / WB) ..; it runs only its own
-// block's K-steps over the shared window.
+// Work-group barrier for LDS hand-offs: waits for this wave's LDS accesses
+// only, so global loads in flight and stores not yet acknowledged stay so.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Block i (0, 1, ..) of the wave's list within its group: waves with the same
+// frames split the group's WB blocks WS ways in snake order (WS = 2, WB = 4:
+// {0, 3} and {1, 2}), which evens out the K ranges when they grow with the
+// block index.  With one block per wave (WS = WB) the assignment rotates with
+// the tile so that the widest block does not always land on the same SIMD.
+__device__ __forceinline__ int wave_block(int i, int ws, int WS, int WB, int tile) {
+    if (WS == WB) return i == 0 ? (ws + tile) % WB : WB;
+    const int r = i >> 1;
+    return (i & 1) ? 2 * WS * r + 2 * WS - 1 - ws : 2 * WS * r + ws;
+}
+
+// K-steps, MFMAs and epilogue of one block for the wave's A frame blocks
+// (fb0 ..); ta/tb hold the block's first eight tap fragments on entry.
 template <int DT, int A>
-__device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
-                                                 uint8_t* lds, float* red) {
-    using T = Tr<DT>;
-    const int WB = c.wb, WF = kMfmaWaves / WB, F = 32 * A * WF;
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, const Geo& g, const uint8_t* lds,
+                                          const MfmaBlock* __restrict__ B, int glo, int64_t k0, int fb0,
+                                          float inv_beta, Frag<DT> (&ta)[4], Frag<DT> (&tb)[4]) {
+    const int lane = threadIdx.x & 63;
     const int n = lane & 31, hg = lane >> 5;
-    const int wf = w / WB, wb = w - wf * WB;
-    const int64_t k0 = (int64_t)tile * F;
-    const int b0 = grp * WB, nb = min(WB, a.ngroups - b0);
-    int glo = a.blocks[b0].lo, ghi = a.blocks[b0].hi;
-    for (int i = 1; i < nb; ++i) {
-        glo = min(glo, a.blocks[b0 + i].lo);
-        ghi = max(ghi, a.blocks[b0 + i].hi);
-    }
-    const int slot = (wb + tile) % WB;
-    const bool has = slot < nb;
-    const MfmaBlock* __restrict__ B = a.blocks + b0 + (has ? slot : 0);
     const int lo = B->lo, hi = B->hi;
     const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
-    const Geo g = make_geo<DT>(c, F, ghi - glo + 1);
-    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
-    float beta = 1.0f;
-    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
-    auto tap = [&](int ks) { return tbase + (int64_t)(min(ks, hi) - lo) * T::STEP; };
-
-    // the first eight tap fragments are in flight while the window is staged
-    Frag<DT> ta[4], tb[4];
-    if (has) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            load_tap<DT>(tap(lo + j), lane, ta[j]);
-            load_tap<DT>(tap(lo + 4 + j), lane, tb[j]);
-        }
-    }
-    win_stage<DT, WinOcc<DT, A>::SF>(c, g, k0 * c.hop + (int64_t)T::KS * glo, al16, beta, lds);
-    __syncthreads();
-    if (!has) return;
-
     f32x16 acc[A];
 #pragma unroll
     for (int fa = 0; fa < A; ++fa)
@@ -875,19 +897,17 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
         for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
     int base[A], unit0[A];
     if (g.swz >= 0) {
-        lane_bases<DT, A, LM_LINEAR_SWZ>(c, g, A * wf, base, unit0);
+        lane_bases<DT, A, LM_LINEAR_SWZ>(c, g, fb0, base, unit0);
         compute_chunk<DT, A, LM_LINEAR_SWZ>(lds, g, g.swz, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase,
                                             ta, tb, acc);
     } else {
-        lane_bases<DT, A, LM_LINEAR>(c, g, A * wf, base, unit0);
+        lane_bases<DT, A, LM_LINEAR>(c, g, fb0, base, unit0);
         compute_chunk<DT, A, LM_LINEAR>(lds, g, 31, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase, ta, tb,
                                         acc);
     }
-
-    const float inv_beta = 1.0f / beta;
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
-        const int64_t k = k0 + 32 * (A * wf + fa) + n;
+        const int64_t k = k0 + 32 * (fb0 + fa) + n;
         if (k >= c.K) continue;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -899,6 +919,51 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
             if (!a.signed_out) val = fabsf(val);
             __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
         }
+    }
+}
+
+// WIN tile: F = 32*A*(4/WS) consecutive frames against the WB consecutive
+// 32-scale blocks of group grp, over one shared window.  Wave w takes frame
+// group w / WS (A frame blocks) and runs its share of the group's blocks
+// (wave_block) one after the other: the stores of one block drain while the
+// next one's MFMAs run.
+template <int DT, int A>
+__device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
+                                                 uint8_t* lds, float* red) {
+    using T = Tr<DT>;
+    const int WB = c.wb, WS = c.ws, WF = kMfmaWaves / WS, F = 32 * A * WF;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wf = w / WS, ws = w - wf * WS;
+    const int64_t k0 = (int64_t)tile * F;
+    const int b0 = grp * WB, nb = min(WB, a.ngroups - b0);
+    int glo = a.blocks[b0].lo, ghi = a.blocks[b0].hi;
+    for (int i = 1; i < nb; ++i) {
+        glo = min(glo, a.blocks[b0 + i].lo);
+        ghi = max(ghi, a.blocks[b0 + i].hi);
+    }
+    const Geo g = make_geo<DT>(c, F, ghi - glo + 1);
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
+    float beta = 1.0f;
+    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
+    const float inv_beta = 1.0f / beta;
+
+    // taps of the first eight steps of the wave's first block
+    int j = wave_block(0, ws, WS, WB, tile);
+    Frag<DT> ta[4], tb[4];
+    auto prefetch = [&](const MfmaBlock* __restrict__ B) {
+        const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            load_tap<DT>(tbase + (int64_t)s * T::STEP, lane, ta[s]);
+            load_tap<DT>(tbase + (int64_t)(4 + s) * T::STEP, lane, tb[s]);
+        }
+    };
+    if (j < nb) prefetch(a.blocks + b0 + j);
+    win_stage<DT, WinOcc<DT, A>::SF>(c, g, k0 * c.hop + (int64_t)T::KS * glo, al16, beta, lds);
+    lds_barrier();
+    for (int i = 0; j < nb; j = wave_block(++i, ws, WS, WB, tile)) {
+        if (i > 0) prefetch(a.blocks + b0 + j);
+        win_block<DT, A>(a, c, g, lds, a.blocks + b0 + j, glo, k0, A * wf, inv_beta, ta, tb);
     }
 }
 
@@ -969,19 +1034,27 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
         lo = __builtin_amdgcn_readfirstlane(lo);   // uniform: the descriptor stays scalar
         const int local = t - (in_lds ? spre[lo] : a.tile_prefix[lo]);
         const ClipArg c = a.clips[lo];
-        if (!ANY || c.mode == STAGE_WIN) {
+        if constexpr (ANY) {
+            if (c.mode == STAGE_LINEAR) {
+                const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
+                process_tile<DT, A>(a, c, tile, blk, lds, red);
+                lds_barrier();
+                continue;
+            }
+            if (c.mode == STAGE_ROWS) {
+                const int ng = (a.ngroups + a.split_wb - 1) / a.split_wb;
+                const int tile = local / ng, grp = local - tile * ng;
+                process_tile_split<DT>(a, c, tile, grp, lds, red);
+                lds_barrier();
+                continue;
+            }
+        }
+        {
             const int ng = (a.ngroups + c.wb - 1) / c.wb;
             const int tile = local / ng, grp = local - tile * ng;
             process_tile_win<DT, A>(a, c, tile, grp, lds, red);
-        } else if (c.mode == STAGE_LINEAR) {
-            const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
-            process_tile<DT, A>(a, c, tile, blk, lds, red);
-        } else {
-            const int ng = (a.ngroups + a.split_wb - 1) / a.split_wb;
-            const int tile = local / ng, grp = local - tile * ng;
-            process_tile_split<DT>(a, c, tile, grp, lds, red);
         }
-        __syncthreads();                        // LDS free for the next tile
+        lds_barrier();                          // LDS free for the next tile
     }
 }
 
@@ -1006,35 +1079,60 @@ void k_mfma_persistent_win(MfmaArgs a) {
 // table, reductions).
 static int dyn_lds_max() { return mfma_max_lds_bytes() - 8192; }
 
+// A = 8 (256 frames per wave) exists for the WIN kernels of the 2-byte types only.
+template <int DT, int A>
+constexpr bool kWinOnly = A == 8;
+template <int DT, int A>
+constexpr bool kHasA = A != 8 || DT == DT_BF16 || DT == DT_FP16;
+
 template <int DT, int A>
 static hipError_t launch2(const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
     const size_t shm = (size_t)a.shm_bytes;
     if (shm > (size_t)dyn_lds_max()) return hipErrorInvalidValue;
-    (void)hipGetLastError();   // report only this launch's error
-    if (persistent == 2)
-        hipLaunchKernelGGL((k_mfma_persistent_win<DT, A>), dim3(grid), dim3(256), shm, s, a);
-    else if (persistent)
-        hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
-    else if (a.clip.mode == STAGE_WIN)
-        hipLaunchKernelGGL((k_mfma_win<DT, A>), dim3(grid), dim3(256), shm, s, a);
-    else if (a.clip.mode == STAGE_ROWS)
-        hipLaunchKernelGGL((k_mfma_split<DT>), dim3(grid), dim3(256), shm, s, a);
-    else
-        hipLaunchKernelGGL((k_mfma_grid<DT, A>), dim3(grid), dim3(256), shm, s, a);
-    return hipGetLastError();
+    if constexpr (!kHasA<DT, A>) {
+        return hipErrorInvalidValue;
+    } else {
+        const bool win = persistent == 2 || (!persistent && a.clip.mode == STAGE_WIN);
+        if (kWinOnly<DT, A> && !win) return hipErrorInvalidValue;
+        (void)hipGetLastError();   // report only this launch's error
+        if (persistent == 2) {
+            hipLaunchKernelGGL((k_mfma_persistent_win<DT, A>), dim3(grid), dim3(256), shm, s, a);
+        } else if (win) {
+            hipLaunchKernelGGL((k_mfma_win<DT, A>), dim3(grid), dim3(256), shm, s, a);
+        } else if constexpr (!kWinOnly<DT, A>) {
+            if (persistent)
+                hipLaunchKernelGGL((k_mfma_persistent<DT, A>), dim3(grid), dim3(256), shm, s, a);
+            else if (a.clip.mode == STAGE_ROWS)
+                hipLaunchKernelGGL((k_mfma_split<DT>), dim3(grid), dim3(256), shm, s, a);
+            else
+                hipLaunchKernelGGL((k_mfma_grid<DT, A>), dim3(grid), dim3(256), shm, s, a);
+        }
+        return hipGetLastError();
+    }
 }
 
 template <int DT, int A>
 static hipError_t attrs2() {
     const int lds = dyn_lds_max();
-    const void* fns[5] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A>,
-                          (const void*)k_mfma_split<DT>, (const void*)k_mfma_win<DT, A>,
-                          (const void*)k_mfma_persistent_win<DT, A>};
-    for (const void* fn : fns) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return e;
+    if constexpr (!kHasA<DT, A>) {
+        return hipSuccess;
+    } else if constexpr (kWinOnly<DT, A>) {
+        const void* fns[2] = {(const void*)k_mfma_win<DT, A>, (const void*)k_mfma_persistent_win<DT, A>};
+        for (const void* fn : fns) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    } else {
+        const void* fns[5] = {(const void*)k_mfma_persistent<DT, A>, (const void*)k_mfma_grid<DT, A>,
+                              (const void*)k_mfma_split<DT>, (const void*)k_mfma_win<DT, A>,
+                              (const void*)k_mfma_persistent_win<DT, A>};
+        for (const void* fn : fns) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
-    return hipSuccess;
 }
 
 template <int DT>
@@ -1042,6 +1140,7 @@ static hipError_t attrs1() {
     hipError_t e = attrs2<DT, 1>();
     if (e == hipSuccess) e = attrs2<DT, 2>();
     if (e == hipSuccess) e = attrs2<DT, 4>();
+    if (e == hipSuccess) e = attrs2<DT, 8>();
     return e;
 }
 
@@ -1055,9 +1154,13 @@ hipError_t mfma_init_attributes() {
 
 template <int DT>
 static hipError_t launch1(int A, const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
-    if (A == 1) return launch2<DT, 1>(a, persistent, grid, s);
-    if (A == 2) return launch2<DT, 2>(a, persistent, grid, s);
-    return launch2<DT, 4>(a, persistent, grid, s);
+    switch (A) {
+        case 1: return launch2<DT, 1>(a, persistent, grid, s);
+        case 2: return launch2<DT, 2>(a, persistent, grid, s);
+        case 4: return launch2<DT, 4>(a, persistent, grid, s);
+        case 8: return launch2<DT, 8>(a, persistent, grid, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_mfma(int dt, int A, int, const MfmaArgs& a, int persistent, int grid, hipStream_t s) {
@@ -1074,17 +1177,25 @@ int mfma_max_lds_bytes() { return 160 * 1024; }
 
 template <int DT, int A>
 static int occ2(int persistent, size_t shm) {
-    int n = 0;
-    const void* fn = persistent == 2 ? (const void*)k_mfma_persistent_win<DT, A>
-                     : persistent ? (const void*)k_mfma_persistent<DT, A> : (const void*)k_mfma_win<DT, A>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, shm) != hipSuccess) return 1;
-    return n;
+    if constexpr (!kHasA<DT, A>) {
+        return 1;
+    } else {
+        int n = 0;
+        const void* fn = persistent == 2 ? (const void*)k_mfma_persistent_win<DT, A> : (const void*)k_mfma_win<DT, A>;
+        if constexpr (!kWinOnly<DT, A>)
+            if (persistent == 1) fn = (const void*)k_mfma_persistent<DT, A>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, shm) != hipSuccess) return 1;
+        return n;
+    }
 }
 template <int DT>
 static int occ1(int A, int persistent, size_t shm) {
-    if (A == 1) return occ2<DT, 1>(persistent, shm);
-    if (A == 2) return occ2<DT, 2>(persistent, shm);
-    return occ2<DT, 4>(persistent, shm);
+    switch (A) {
+        case 1: return occ2<DT, 1>(persistent, shm);
+        case 2: return occ2<DT, 2>(persistent, shm);
+        case 4: return occ2<DT, 4>(persistent, shm);
+        default: return occ2<DT, 8>(persistent, shm);
+    }
 }
 int mfma_occupancy(int dt, int A, int, int persistent, size_t shm) {
     switch (dt) {

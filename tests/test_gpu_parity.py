@@ -363,6 +363,28 @@ def test_prepared_batches_replay(torch, cw):
                 assert torch.equal(a, b), (rep, j)
 
 
+def test_batch_context_on_two_streams(torch, cw):
+    """One context fed alternately from two streams with changing batches."""
+    scales = np.arange(1, 65)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (1, 64, 512)}
+    B = cw.Batch(32)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    runs = []
+    for rep in range(6):
+        xs, hs = _batch_inputs(torch, 40 + rep % 3, 12, [1, 64, 512], lo=2000, hi=20000)
+        pl = [plans[h] for h in hs]
+        alone = [p(x) for p, x in zip(pl, xs)]
+        torch.cuda.synchronize()
+        st = streams[rep % 2]
+        with torch.cuda.stream(st):
+            outs = B(pl, xs, stream=st, graph=bool(rep % 2))
+        runs.append((alone, outs))
+    torch.cuda.synchronize()
+    for rep, (alone, outs) in enumerate(runs):
+        for a, b in zip(alone, outs):
+            assert torch.equal(a, b), rep
+
+
 def test_batch_graph_replays(torch, cw):
     scales = np.arange(1, 129)
     plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (64, 256, 512)}
