@@ -123,12 +123,15 @@ cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs,
                              void* stream);
 
 /*
- * Explicit batch context: owns pinned and device descriptor buffers sized for
- * up to max_clips clips and a captured HIP graph (descriptor upload + the
- * persistent launch) that cwt_batch_execute replays with new descriptor
- * contents.  One context serves one stream at a time; calls on it are
- * serialised by the host (a call waits until the previous replay has consumed
- * its descriptors).
+ * Explicit batch context: owns two pinned and two device descriptor buffers
+ * sized for up to max_clips clips and captured HIP graphs (descriptor upload +
+ * the persistent launch, or the launch alone) that cwt_batch_execute replays.
+ * A batch whose descriptors equal those already held by one of the device
+ * buffers (the same plans, buffers and lengths run again) is launched without
+ * an upload.  Calls on one context are serialised by a mutex; a call may wait
+ * on the host until the pinned buffer it reuses has been consumed (two calls
+ * back), and a device buffer is overwritten only after the launches that read
+ * it have completed, also when they were queued on another stream.
  */
 cwt_status cwt_batch_create(int32_t max_clips, cwt_batch_t* batch_out);
 cwt_status cwt_batch_destroy(cwt_batch_t batch);
