@@ -82,6 +82,8 @@ def parse():
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--hop-sweep", action="store_true",
                     help="cost curve over hops 1, 2, 4, .., 1024 (one JSON line per hop) instead of the metric")
+    ap.add_argument("--decimate", action="store_true",
+                    help="decimate-then-transform against the hop-strided transform, hops 2 .. 512 (JSON lines)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -155,6 +157,53 @@ def hop_sweep(torch, cwth, synth, dev, scales, args):
             row["bf16"]["bound"], row["fp32"]["coeffs_per_s"], row["ratio_bf16_over_fp32"]))
 
 
+def decimate_sweep(torch, cwth, synth, dev, scales, args):
+    """The two readings of the paper's hop on one 10 s clip (128 scales, BF16):
+    the hop-strided transform (Sec. II-B) against decimating the signal by the
+    hop (plain, and with a 8h+1-tap anti-alias filter) and transforming the
+    decimated signal at hop 1 with scales s/h (Sec. III-B).  Reports the device
+    time of each route and the deviation of sqrt(h) times the decimated route's
+    signed W from the hop-strided W (the sqrt(h) is the 1/sqrt(s) normalisation
+    at the coarser sampling)."""
+    x = torch.from_numpy(synth.make_clip(synth.clip_seed(2, 60), N, FS, 0.0)).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for hop in [1 << k for k in range(1, 10)]:
+        ref_plan = cwth.Plan(FS, scales, hop, "bf16", signed=True)
+        ref = ref_plan(x)
+        t_ref = timed(lambda: ref_plan.execute(x, ref, stream), 20)
+        row = {"hop": hop, "hop_strided_us": 1e3 * t_ref}
+        dec_plan = cwth.Plan(FS / hop, scales / hop, 1, "bf16", signed=True)
+        for name, h in (("plain", None), ("fir", torch.from_numpy(cwth.lowpass_fir(hop, 8 * hop + 1)
+                                                                 .astype(np.float32)).to(dev))):
+            y = cwth.decimate(x, hop, h)
+            w = dec_plan(y)
+            t = timed(lambda: (cwth.decimate(x, hop, h, out=y, stream=stream), dec_plan.execute(y, w, stream)), 20)
+            d = (w.double() * math.sqrt(hop) - ref.double())
+            rel = float(d.norm() / ref.double().norm())
+            keep = torch.from_numpy(np.asarray(scales) >= 2 * hop).to(dev)   # scales resolved after decimation
+            rel_res = float(d[keep].norm() / ref.double()[keep].norm()) if bool(keep.any()) else None
+            row[name] = {"us": 1e3 * t, "rel_l2_vs_hop_strided": rel, "rel_l2_scales_ge_2hop": rel_res}
+        print(json.dumps({"metric": "decimate-then-transform vs hop-strided transform, 10 s clip, 128 scales, bf16",
+                          **row}), flush=True)
+        log("hop %3d: strided %.1f us; decimate+cwt %.1f us (plain, dev %.3f / %s), %.1f us (fir, dev %.3f / %s)" % (
+            hop, row["hop_strided_us"], row["plain"]["us"], row["plain"]["rel_l2_vs_hop_strided"],
+            row["plain"]["rel_l2_scales_ge_2hop"], row["fir"]["us"], row["fir"]["rel_l2_vs_hop_strided"],
+            row["fir"]["rel_l2_scales_ge_2hop"]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -183,6 +232,9 @@ def main():
     scales = synth.linear_scales(S)
     if args.hop_sweep:
         hop_sweep(torch, cwth, synth, dev, scales, args)
+        return
+    if args.decimate:
+        decimate_sweep(torch, cwth, synth, dev, scales, args)
         return
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame

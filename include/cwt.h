@@ -166,6 +166,40 @@ cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
 cwt_status cwt_plan_bank_taps(cwt_plan_t plan, int32_t scale_index, double* taps_out,
                               int64_t cap);
 
+/* ------------------------------------------------------------------------
+ * Decimate-then-transform (the paper's workflow description, Sec. III-B: the
+ * signal is re-sampled and the re-sampled signal is transformed).  The
+ * transform of the decimated signal is a hop-1 plan at scales s / factor.
+ */
+
+/* ceil(len / factor); -1 if len < 0 or factor < 1. */
+int64_t cwt_decimated_length(int64_t len, int32_t factor);
+
+/*
+ * Anti-alias filter for decimation by `factor` (host, FP64): n_taps (odd,
+ * >= 1) windowed-sinc taps with cutoff fs/(2 factor) and a Hamming window,
+ * h[j] = w[j] sinc((j - c)/factor)/factor, c = (n_taps-1)/2,
+ * w[j] = 0.54 - 0.46 cos(2 pi j/(n_taps-1)), scaled to unit DC gain.
+ * h_out: host double[n_taps].  Errors: CWT_ERR_INVALID_ARG (factor < 1,
+ * n_taps even or < 1, NULL h_out).
+ */
+cwt_status cwt_lowpass_fir(int32_t factor, int32_t n_taps, double* h_out);
+
+/*
+ * y[n] = sum_{j=0}^{h_len-1} h[j] * x~[n*factor + j - (h_len-1)/2] for
+ * n = 0 .. cwt_decimated_length(len, factor) - 1, x~ zero outside [0, len):
+ * output sample n sits on input sample n*factor, like frame n of a hop-factor
+ * transform.  x: device float32[len]; h: device float32[h_len] (h_len odd;
+ * h = {1} is plain decimation); y: device float32[cwt_decimated_length].
+ * FP32 accumulation: in ascending j for h_len < 64, else 64 interleaved
+ * partial sums (lane l takes j = l, l + 64, ..) combined by a fixed butterfly;
+ * deterministic either way.  Asynchronous on `stream`.  Errors:
+ * CWT_ERR_INVALID_ARG (len < 0, factor < 1, h_len even or < 1, NULL pointers
+ * when len > 0), CWT_ERR_DEVICE (launch failure).  len == 0 is a no-op.
+ */
+cwt_status cwt_decimate(const float* x, int64_t len, int32_t factor, const float* h, int32_t h_len,
+                        float* y, void* stream);
+
 const char* cwt_status_string(cwt_status s);
 const char* cwt_last_error(void);
 

@@ -121,6 +121,10 @@ hipError_t mfma_init_attributes();
 // Resident work-groups per CU for a kernel instance with `shm` bytes of dynamic LDS.
 int mfma_occupancy(int dt, int A, int nb, int persistent, size_t shm);
 
+// Decimation (decim.hip): y[n] = sum_j h[j] x~[n*factor + j - (L-1)/2].
+hipError_t launch_decimate(const float* x, int64_t len, int factor, const float* h, int L, float* y, int64_t ny,
+                           hipStream_t s);
+
 // Bank generation (bank.hip).
 struct BankScale {      // one sorted scale as the generator sees it
     double s;

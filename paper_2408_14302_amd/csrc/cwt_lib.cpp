@@ -1203,6 +1203,51 @@ cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out) {
     }
 }
 
+int64_t cwt_decimated_length(int64_t len, int32_t factor) {
+    if (len < 0 || factor < 1) return -1;
+    return (len + factor - 1) / factor;
+}
+
+cwt_status cwt_lowpass_fir(int32_t factor, int32_t n_taps, double* h_out) {
+    if (factor < 1) return fail(CWT_ERR_INVALID_ARG, "factor must be >= 1");
+    if (n_taps < 1 || n_taps % 2 == 0) return fail(CWT_ERR_INVALID_ARG, "n_taps must be odd and >= 1");
+    if (!h_out) return fail(CWT_ERR_INVALID_ARG, "h_out is NULL");
+    if (n_taps == 1) {
+        h_out[0] = 1.0;
+        return CWT_OK;
+    }
+    const double c = 0.5 * (n_taps - 1);
+    double sum = 0.0;
+    for (int j = 0; j < n_taps; ++j) {
+        const double t = (j - c) / factor;
+        const double sinc = t == 0.0 ? 1.0 : std::sin(M_PI * t) / (M_PI * t);
+        const double w = 0.54 - 0.46 * std::cos(2.0 * M_PI * j / (n_taps - 1));
+        h_out[j] = w * sinc / factor;
+        sum += h_out[j];
+    }
+    for (int j = 0; j < n_taps; ++j) h_out[j] /= sum;
+    return CWT_OK;
+}
+
+cwt_status cwt_decimate(const float* x, int64_t len, int32_t factor, const float* h, int32_t h_len, float* y,
+                        void* stream) {
+    try {
+        if (len < 0) return fail(CWT_ERR_INVALID_ARG, "len < 0");
+        if (factor < 1) return fail(CWT_ERR_INVALID_ARG, "factor must be >= 1");
+        if (h_len < 1 || h_len % 2 == 0) return fail(CWT_ERR_INVALID_ARG, "h_len must be odd and >= 1");
+        if (len == 0) return CWT_OK;
+        if (!x || !h || !y) return fail(CWT_ERR_INVALID_ARG, "NULL x, h or y");
+        int dev = 0;
+        cwt_status st = current_device(&dev, nullptr);
+        if (st != CWT_OK) return st;
+        HIP_TRY(launch_decimate(x, len, factor, h, h_len, y, (len + factor - 1) / factor, (hipStream_t)stream),
+                "decimate launch");
+        return CWT_OK;
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
 cwt_status cwt_plan_bank_taps(cwt_plan_t plan, int32_t scale_index, double* taps_out, int64_t cap) {
     if (!plan || !taps_out) return fail(CWT_ERR_INVALID_ARG, "NULL argument");
     const Bank& bk = *plan->bank;

@@ -42,6 +42,9 @@ _SIGS = {
     "cwt_plan_num_configs": (_i32, [_c_plan]),
     "cwt_plan_set_config": (_i32, [_c_plan, _i32]),
     "cwt_plan_bank_taps": (_i32, [_c_plan, _i32, _vp, _i64]),
+    "cwt_decimated_length": (_i64, [_i64, _i32]),
+    "cwt_lowpass_fir": (_i32, [_i32, _i32, _vp]),
+    "cwt_decimate": (_i32, [_vp, _i64, _i32, _vp, _i32, _vp, _vp]),
     "cwt_status_string": (ctypes.c_char_p, [_i32]),
     "cwt_last_error": (ctypes.c_char_p, []),
     "cwt_version": (ctypes.c_char_p, []),
@@ -271,6 +274,43 @@ class PreparedBatch:
         _check(_lib.cwt_batch_execute(self.batch._h, self._P, self._X, self._L, self._O, self._n,
                                       1 if graph else 0, _stream_ptr(stream)), "cwt_batch_execute")
         return self.outs
+
+
+def decimated_length(n: int, factor: int) -> int:
+    return int(_lib.cwt_decimated_length(int(n), int(factor)))
+
+
+def lowpass_fir(factor: int, n_taps: int):
+    """Anti-alias filter taps (numpy float64[n_taps], unit DC gain) for
+    decimation by `factor` (cwt_lowpass_fir)."""
+    import numpy as np
+    h = np.empty(int(n_taps), dtype=np.float64)
+    _check(_lib.cwt_lowpass_fir(int(factor), int(n_taps), h.ctypes.data_as(_vp)), "cwt_lowpass_fir")
+    return h
+
+
+def decimate(x, factor: int, h=None, out=None, stream=None):
+    """y[n] = sum_j h[j] x~[n*factor + j - (len(h)-1)/2] on the device
+    (cwt_decimate).  h: None (plain decimation) or a float32 CUDA tensor of odd
+    length."""
+    import torch
+    _check_signal(x)
+    if h is None:
+        h = torch.ones(1, dtype=torch.float32, device=x.device)
+    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float32 and h.dim() == 1
+            and h.is_contiguous()):
+        raise TypeError("h must be a contiguous 1-D float32 CUDA tensor")
+    n = x.numel()
+    ny = decimated_length(n, factor)
+    if ny < 0:
+        raise CwtError(INVALID_ARG, "cwt_decimate")
+    if out is None:
+        out = torch.empty(ny, dtype=torch.float32, device=x.device)
+    elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != ny:
+        raise ValueError("out must be a contiguous float32 tensor of ceil(len / factor) elements")
+    _check(_lib.cwt_decimate(x.data_ptr() if n else None, n, int(factor), h.data_ptr(), h.numel(),
+                             out.data_ptr() if n else None, _stream_ptr(stream)), "cwt_decimate")
+    return out
 
 
 def raw():

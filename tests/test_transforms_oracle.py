@@ -1,0 +1,76 @@
+"""Pins of the oracle's decimation route (decimate-then-transform reading of
+Sec. III-B) and the library's host-side filter design, on the CPU."""
+import numpy as np
+import pytest
+import scipy.signal as ss
+
+import oracle
+from oracle import transforms as T
+
+
+@pytest.mark.parametrize("factor,ntaps", [(2, 17), (3, 25), (4, 33), (8, 65), (64, 513)])
+def test_lowpass_fir_is_the_hamming_windowed_sinc(factor, ntaps):
+    # scipy's window method with the cutoff at 1/factor of Nyquist and unit DC gain
+    ref = ss.firwin(ntaps, 1.0 / factor, window="hamming")
+    np.testing.assert_allclose(T.lowpass_fir(factor, ntaps), ref, rtol=0, atol=1e-15)
+
+
+def test_plain_decimation_is_subsampling():
+    x = np.random.default_rng(1).standard_normal(1003)
+    for f in (1, 2, 5, 64, 2000):
+        np.testing.assert_array_equal(T.decimate(x, f), x[::f])
+        assert len(T.decimate(x, f)) == T.decimated_length(len(x), f)
+
+
+@pytest.mark.parametrize("factor", [2, 3, 8])
+def test_filtered_decimation_matches_upfirdn(factor):
+    # symmetric filter: the centred correlation equals scipy's convolution
+    # followed by downsampling, shifted by the filter's half length
+    x = np.random.default_rng(factor).standard_normal(777)
+    h = T.lowpass_fir(factor, 8 * factor + 1)
+    c = (len(h) - 1) // 2
+    full = ss.upfirdn(h, np.concatenate([x, np.zeros(c)]), up=1, down=1)
+    ref = full[np.arange(T.decimated_length(len(x), factor)) * factor + c]
+    np.testing.assert_allclose(T.decimate(x, factor, h), ref, rtol=0, atol=1e-13)
+
+
+def test_asymmetric_filter_against_a_dense_matrix():
+    # the definition as a matrix: D[n, i] = h[i - n*f + c] for the valid taps
+    rng = np.random.default_rng(5)
+    x, h, f = rng.standard_normal(50), rng.standard_normal(7), 3
+    c = 3
+    n_out = T.decimated_length(len(x), f)
+    D = np.zeros((n_out, len(x)))
+    for n in range(n_out):
+        for i in range(len(x)):
+            j = i - n * f + c
+            if 0 <= j < len(h):
+                D[n, i] = h[j]
+    np.testing.assert_allclose(T.decimate(x, f, h), D @ x, rtol=0, atol=1e-13)
+
+
+def test_unit_dc_gain_keeps_a_constant_in_the_interior():
+    h = T.lowpass_fir(4, 33)
+    y = T.decimate(np.full(400, 0.75), 4, h)
+    np.testing.assert_allclose(y[5:-5], 0.75, rtol=0, atol=1e-14)
+
+
+def test_decimated_cwt_is_the_cwt_of_the_decimated_signal_at_scaled_scales():
+    x = np.random.default_rng(9).standard_normal(256)
+    scales = np.array([2.0, 4.0, 8.0])
+    got = T.decimated_cwt(x, scales, 2)
+    ref = oracle.dense_cwt(x[::2], scales / 2, 1)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+
+
+def test_library_filter_design_matches_the_oracle(lib_or_skip):
+    import ctypes
+    for f, n in ((2, 17), (5, 41), (512, 4097)):
+        h = np.empty(n)
+        assert lib_or_skip.cwt_lowpass_fir(f, n, h.ctypes.data_as(ctypes.c_void_p)) == 0
+        np.testing.assert_allclose(h, T.lowpass_fir(f, n), rtol=0, atol=1e-15)
+    h = np.empty(4)
+    assert lib_or_skip.cwt_lowpass_fir(2, 4, h.ctypes.data_as(ctypes.c_void_p)) == 1   # even length
+    assert lib_or_skip.cwt_lowpass_fir(0, 5, h.ctypes.data_as(ctypes.c_void_p)) == 1
+    assert lib_or_skip.cwt_decimated_length(10, 3) == 4
+    assert lib_or_skip.cwt_decimated_length(-1, 3) == -1
