@@ -84,6 +84,8 @@ def parse():
                     help="cost curve over hops 1, 2, 4, .., 1024 (one JSON line per hop) instead of the metric")
     ap.add_argument("--decimate", action="store_true",
                     help="decimate-then-transform against the hop-strided transform, hops 2 .. 512 (JSON lines)")
+    ap.add_argument("--image", action="store_true",
+                    help="scalogram-to-image step (dB, min-max, bilinear to 224x224) timing (JSON lines)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -204,6 +206,28 @@ def decimate_sweep(torch, cwth, synth, dev, scales, args):
             row["fir"]["rel_l2_scales_ge_2hop"]))
 
 
+def image_bench(torch, cwth, synth, dev, scales, args):
+    """The scalogram-to-image step on the scalograms of one 10 s clip
+    (128 scales) at hops 1 and 512: device time per image and the HBM rate of
+    its dominant pass (the min/max over the whole scalogram, 4 B per
+    coefficient), against the 8 TB/s peak."""
+    x = torch.from_numpy(synth.make_clip(synth.clip_seed(2, 70), N, FS, 0.0)).to(dev)
+    stream = torch.cuda.current_stream()
+    for hop in (1, 512):
+        w = cwth.Plan(FS, scales, hop, "bf16")(x)
+        ws = torch.empty(int(cwth.raw().cwt_image_workspace_bytes()), dtype=torch.uint8, device=dev)
+        img = torch.empty((224, 224), dtype=torch.float32, device=dev)
+        run = lambda: cwth.scalogram_image(w, 224, 224, amin=1e-6, out=img, workspace=ws, stream=stream)
+        total, per = time_launches(torch, lambda s_: run(), 1, max(args.steps, 20), args.warmup)
+        ms = float(np.mean(per))
+        byt = 4.0 * w.numel() + 4.0 * 5 * 224 * 224
+        row = {"hop": hop, "scalogram": list(w.shape), "image": [224, 224], "us_per_image": 1e3 * ms,
+               "bytes": byt, "gb_per_s": byt / (ms * 1e-3) / 1e9, "hbm_frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        print(json.dumps({"metric": "scalogram to image (dB, min-max, bilinear 224x224)", **row}), flush=True)
+        log("image hop %d: %.1f us, %.0f GB/s (%.2f of HBM)" % (hop, row["us_per_image"], row["gb_per_s"],
+                                                                 row["hbm_frac"]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -235,6 +259,9 @@ def main():
         return
     if args.decimate:
         decimate_sweep(torch, cwth, synth, dev, scales, args)
+        return
+    if args.image:
+        image_bench(torch, cwth, synth, dev, scales, args)
         return
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame

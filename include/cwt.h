@@ -200,6 +200,36 @@ cwt_status cwt_lowpass_fir(int32_t factor, int32_t n_taps, double* h_out);
 cwt_status cwt_decimate(const float* x, int64_t len, int32_t factor, const float* h, int32_t h_len,
                         float* y, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Scalogram to image: the step after the transform, where scalograms become
+ * the CNN's input images (Sec. II-A with Fig. 1, Sec. III-B).
+ *
+ *   D[i][k]     = 20 log10(max(|W[i][k]|, amin))
+ *   image[r][c] = (B(r, c) - min D) / (max D - min D),  0 if max D == min D
+ *
+ * B is D resampled bilinearly to height x width with half-pixel centres (the
+ * source row of output row r is (r + 0.5) * n_scales / height - 0.5, clamped
+ * below at 0, interpolating rows floor(.) and floor(.) + 1 or the last row;
+ * likewise columns over frames; no anti-aliasing); min and max over the full
+ * n_scales x n_frames D.
+ */
+
+/* Bytes of device workspace cwt_scalogram_image needs (partial extrema). */
+int64_t cwt_image_workspace_bytes(void);
+
+/*
+ * scalogram: device float32[n_scales][n_frames] (|W| or signed W; the
+ * magnitude is taken); image: device float32[height][width]; workspace:
+ * device buffer of cwt_image_workspace_bytes() bytes, owned by the caller, not
+ * shared by calls in flight at the same time.  FP32 arithmetic (log10f; source
+ * coordinates in double).  Asynchronous on `stream`.  Errors:
+ * CWT_ERR_INVALID_ARG (n_scales, n_frames, height or width < 1, amin not
+ * finite and > 0, NULL pointers), CWT_ERR_DEVICE (launch failure).
+ */
+cwt_status cwt_scalogram_image(const float* scalogram, int32_t n_scales, int64_t n_frames, float amin,
+                               float* image, int32_t height, int32_t width, void* workspace,
+                               void* stream);
+
 const char* cwt_status_string(cwt_status s);
 const char* cwt_last_error(void);
 

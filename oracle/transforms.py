@@ -69,3 +69,48 @@ def decimated_cwt(x, scales, factor: int, h=None) -> np.ndarray:
     decimated signal at scales s / factor, i.e. the same scales in seconds."""
     y = decimate(x, factor, h)
     return _cwt(y, np.asarray(scales, dtype=np.float64) / factor, 1)
+
+
+# ---------------------------------------------------------------------------
+# Scalogram to image (Sec. II-A with Fig. 1, Sec. III-B: the scalograms are
+# the CNN's input images).  Readings (the paper gives no formula): decibels
+# of the magnitude with an amplitude floor, bilinear resampling with
+# half-pixel centres and no anti-aliasing, min-max normalisation over the
+# full-resolution image.
+
+def to_db(w, amin: float) -> np.ndarray:
+    """D = 20 log10(max(|W|, amin))."""
+    return 20.0 * np.log10(np.maximum(np.abs(np.asarray(w, dtype=np.float64)), float(amin)))
+
+
+def _axis_weights(n_in: int, n_out: int):
+    """Source index pairs and weights of one axis: src = (dst + 0.5) * n_in / n_out - 0.5,
+    clamped below at 0; i0 = floor(src), i1 = i0 + 1 unless i0 is the last index."""
+    src = (np.arange(n_out, dtype=np.float64) + 0.5) * (n_in / n_out) - 0.5
+    src = np.maximum(src, 0.0)
+    i0 = np.floor(src).astype(np.int64)
+    i0 = np.minimum(i0, n_in - 1)
+    i1 = np.where(i0 < n_in - 1, i0 + 1, i0)
+    lam = src - i0
+    return i0, i1, lam
+
+
+def bilinear(img, height: int, width: int) -> np.ndarray:
+    """Bilinear resampling of a 2-D array to height x width (half-pixel centres)."""
+    img = np.asarray(img, dtype=np.float64)
+    r0, r1, wr = _axis_weights(img.shape[0], int(height))
+    c0, c1, wc = _axis_weights(img.shape[1], int(width))
+    top = img[r0][:, c0] * (1.0 - wc) + img[r0][:, c1] * wc
+    bot = img[r1][:, c0] * (1.0 - wc) + img[r1][:, c1] * wc
+    return top * (1.0 - wr)[:, None] + bot * wr[:, None]
+
+
+def scalogram_image(w, amin: float, height: int, width: int) -> np.ndarray:
+    """image = (bilinear(D) - min D) / (max D - min D), min and max over the
+    full-resolution D = to_db(w, amin); all zeros when max D == min D."""
+    d = to_db(w, amin)
+    lo, hi = float(d.min()), float(d.max())
+    b = bilinear(d, height, width)
+    if hi == lo:
+        return np.zeros_like(b)
+    return (b - lo) / (hi - lo)

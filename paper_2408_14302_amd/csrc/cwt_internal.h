@@ -125,6 +125,11 @@ int mfma_occupancy(int dt, int A, int nb, int persistent, size_t shm);
 hipError_t launch_decimate(const float* x, int64_t len, int factor, const float* h, int L, float* y, int64_t ny,
                            hipStream_t s);
 
+// Scalogram image (image.hip): dB, bilinear resize, min-max over the full scalogram.
+int64_t image_workspace_bytes();
+hipError_t launch_image(const float* w, int n_scales, int64_t n_frames, float amin, float* image, int height,
+                        int width, void* workspace, hipStream_t s);
+
 // Bank generation (bank.hip).
 struct BankScale {      // one sorted scale as the generator sees it
     double s;

@@ -1203,6 +1203,27 @@ cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out) {
     }
 }
 
+int64_t cwt_image_workspace_bytes(void) { return image_workspace_bytes(); }
+
+cwt_status cwt_scalogram_image(const float* scalogram, int32_t n_scales, int64_t n_frames, float amin, float* image,
+                               int32_t height, int32_t width, void* workspace, void* stream) {
+    try {
+        if (n_scales < 1 || n_frames < 1 || height < 1 || width < 1)
+            return fail(CWT_ERR_INVALID_ARG, "n_scales, n_frames, height and width must be >= 1");
+        if (!(amin > 0.0f) || !std::isfinite(amin)) return fail(CWT_ERR_INVALID_ARG, "amin must be finite and > 0");
+        if (!scalogram || !image || !workspace) return fail(CWT_ERR_INVALID_ARG, "NULL scalogram, image or workspace");
+        if ((int64_t)n_scales > INT64_MAX / n_frames) return fail(CWT_ERR_INVALID_ARG, "scalogram size overflows");
+        int dev = 0;
+        cwt_status st = current_device(&dev, nullptr);
+        if (st != CWT_OK) return st;
+        HIP_TRY(launch_image(scalogram, n_scales, n_frames, amin, image, height, width, workspace,
+                             (hipStream_t)stream), "image launch");
+        return CWT_OK;
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
 int64_t cwt_decimated_length(int64_t len, int32_t factor) {
     if (len < 0 || factor < 1) return -1;
     return (len + factor - 1) / factor;

@@ -42,6 +42,8 @@ _SIGS = {
     "cwt_plan_num_configs": (_i32, [_c_plan]),
     "cwt_plan_set_config": (_i32, [_c_plan, _i32]),
     "cwt_plan_bank_taps": (_i32, [_c_plan, _i32, _vp, _i64]),
+    "cwt_image_workspace_bytes": (_i64, []),
+    "cwt_scalogram_image": (_i32, [_vp, _i32, _i64, ctypes.c_float, _vp, _i32, _i32, _vp, _vp]),
     "cwt_decimated_length": (_i64, [_i64, _i32]),
     "cwt_lowpass_fir": (_i32, [_i32, _i32, _vp]),
     "cwt_decimate": (_i32, [_vp, _i64, _i32, _vp, _i32, _vp, _vp]),
@@ -310,6 +312,23 @@ def decimate(x, factor: int, h=None, out=None, stream=None):
         raise ValueError("out must be a contiguous float32 tensor of ceil(len / factor) elements")
     _check(_lib.cwt_decimate(x.data_ptr() if n else None, n, int(factor), h.data_ptr(), h.numel(),
                              out.data_ptr() if n else None, _stream_ptr(stream)), "cwt_decimate")
+    return out
+
+
+def scalogram_image(w, height: int, width: int, amin: float = 1e-6, out=None, workspace=None, stream=None):
+    """The scalogram as a [height, width] image in [0, 1] (cwt_scalogram_image):
+    dB of |W| floored at amin, bilinear resize, min-max over the full scalogram.
+    w: float32 CUDA tensor [n_scales, n_frames]."""
+    import torch
+    if not (isinstance(w, torch.Tensor) and w.is_cuda and w.dtype == torch.float32 and w.dim() == 2
+            and w.is_contiguous()):
+        raise TypeError("w must be a contiguous 2-D float32 CUDA tensor")
+    if out is None:
+        out = torch.empty((int(height), int(width)), dtype=torch.float32, device=w.device)
+    if workspace is None:
+        workspace = torch.empty(int(_lib.cwt_image_workspace_bytes()), dtype=torch.uint8, device=w.device)
+    _check(_lib.cwt_scalogram_image(w.data_ptr(), w.shape[0], w.shape[1], float(amin), out.data_ptr(), int(height),
+                                    int(width), workspace.data_ptr(), _stream_ptr(stream)), "cwt_scalogram_image")
     return out
 
 

@@ -74,3 +74,51 @@ def test_decimate_then_transform_matches_oracle(torch, cw, factor, filtered):
     assert got.shape == ref.shape
     assert_close("bf16", got, ref, "decimate %d then transform" % factor,
                  scale=gain(scales / factor, float(np.abs(x).max())))
+
+
+# ---------------------------------------------------------------------------
+# Scalogram to image.  Same float32 scalogram in, so the bound is the FP32
+# arithmetic: D carries a few ulp of its magnitude (log10f <= 2 ulp, x20, the
+# bilinear sum), |D| <= 20 log10(1/amin) = 120 dB at amin = 1e-6 (ulp 7.6e-6),
+# so pixels agree within 8 ulp(120) / (max D - min D) <= 2e-6 for a dB range
+# of 30 or more; the test allows 2e-5.
+
+IMG_TOL = 2e-5
+
+
+@pytest.mark.parametrize("shape,size", [((128, 16000), (224, 224)), ((64, 313), (224, 224)), ((8, 50), (100, 300)),
+                                        ((128, 160000), (224, 224)), ((1, 1), (3, 3)), ((32, 40), (32, 40))])
+def test_image_matches_oracle_on_the_same_scalogram(torch, cw, shape, size):
+    rng = np.random.default_rng(shape[1])
+    w = (rng.standard_normal(shape) * np.exp(rng.uniform(-8, 0, shape))).astype(np.float32)
+    w[0, 0] = 0.0                                     # below the floor
+    ref = T.scalogram_image(w.astype(np.float64), 1e-6, *size)
+    got = cw.scalogram_image(_dev(torch, w), *size, amin=1e-6).cpu().numpy()
+    rel, mab = errors(got, ref)
+    print("image %s -> %s max-abs %.2e rel-L2 %.2e" % (shape, size, mab, rel))
+    assert got.shape == tuple(size) and mab <= IMG_TOL
+
+
+def test_image_of_a_transform_end_to_end(torch, cw):
+    # signal -> plain FP32 transform on the device -> image, against the FP64
+    # oracle's transform and image: the FP32 path's relative error ~1e-6 moves
+    # a dB value by ~1e-5 dB except next to zeros of W, which the floor bounds
+    x = synth.make_clip(990, 32000, 16000.0, 0.0)
+    scales = np.arange(1, 65, dtype=np.float64)
+    plan = cw.Plan(16000.0, scales, 1, "fp32")
+    got = cw.scalogram_image(plan(_dev(torch, x)), 224, 224, amin=1e-6).cpu().numpy()
+    ref = T.scalogram_image(oracle.cwt(x.astype(np.float64), scales, 1), 1e-6, 224, 224)
+    rel, mab = errors(got, ref)
+    print("image end to end (fp32): max-abs %.2e rel-L2 %.2e" % (mab, rel))
+    assert rel <= 1e-4 and np.median(np.abs(got - ref)) <= 1e-5
+
+
+def test_image_invalid_arguments(torch, cw):
+    w = torch.ones((4, 5), device="cuda")
+    with pytest.raises(cw.CwtError):
+        cw.scalogram_image(w, 0, 3)
+    with pytest.raises(cw.CwtError):
+        cw.scalogram_image(w, 3, 3, amin=0.0)
+    img = cw.scalogram_image(w, 3, 3)
+    torch.cuda.synchronize()
+    assert float(img.abs().max()) == 0.0              # constant scalogram -> zeros

@@ -74,3 +74,36 @@ def test_library_filter_design_matches_the_oracle(lib_or_skip):
     assert lib_or_skip.cwt_lowpass_fir(0, 5, h.ctypes.data_as(ctypes.c_void_p)) == 1
     assert lib_or_skip.cwt_decimated_length(10, 3) == 4
     assert lib_or_skip.cwt_decimated_length(-1, 3) == -1
+
+
+# ---------------------------------------------------------------------------
+# Scalogram to image.
+
+@pytest.mark.parametrize("shape,size", [((37, 1001), (224, 224)), ((128, 160), (64, 50)), ((8, 50), (224, 224)),
+                                        ((5, 7), (5, 7)), ((1, 300), (1, 33))])
+def test_bilinear_is_torch_interpolate(shape, size):
+    torch = pytest.importorskip("torch")
+    img = np.random.default_rng(sum(shape)).standard_normal(shape)
+    ref = torch.nn.functional.interpolate(torch.from_numpy(img)[None, None], size=size, mode="bilinear",
+                                          align_corners=False, antialias=False)[0, 0].numpy()
+    np.testing.assert_allclose(T.bilinear(img, *size), ref, rtol=0, atol=1e-12)
+
+
+def test_bilinear_reproduces_an_affine_image_when_downsampling():
+    r, c = np.meshgrid(np.arange(40.0), np.arange(3000.0), indexing="ij")
+    img = 0.3 * r - 0.002 * c + 7.0
+    out = T.bilinear(img, 16, 200)
+    rr = (np.arange(16) + 0.5) * 40 / 16 - 0.5
+    cc = (np.arange(200) + 0.5) * 3000 / 200 - 0.5
+    np.testing.assert_allclose(out, 0.3 * rr[:, None] - 0.002 * cc[None, :] + 7.0, rtol=0, atol=1e-11)
+
+
+def test_image_identity_size_constant_and_floor():
+    w = np.random.default_rng(3).standard_normal((6, 9))
+    d = 20 * np.log10(np.abs(w))
+    np.testing.assert_allclose(T.scalogram_image(w, 1e-12, 6, 9), (d - d.min()) / (d.max() - d.min()), atol=1e-14)
+    assert np.all(T.scalogram_image(np.full((4, 5), 2.0), 1e-6, 3, 3) == 0.0)
+    z = np.zeros((3, 4))
+    z[1, 2] = 1.0                                   # one sample above the floor
+    img = T.scalogram_image(z, 1e-3, 3, 4)          # floor -60 dB, peak 0 dB
+    assert img[1, 2] == 1.0 and img.sum() == 1.0
