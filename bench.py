@@ -86,6 +86,9 @@ def parse():
                     help="decimate-then-transform against the hop-strided transform, hops 2 .. 512 (JSON lines)")
     ap.add_argument("--image", action="store_true",
                     help="scalogram-to-image step (dB, min-max, bilinear to 224x224) timing (JSON lines)")
+    ap.add_argument("--dwt", action="store_true",
+                    help="DWT scalogram (db4, 14 levels) on 3 and 256 clips of 10 s, against the CWTH (JSON lines)")
+    ap.add_argument("--dwt-clips", default="3,256", help="batch sizes for --dwt (comma separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -228,6 +231,44 @@ def image_bench(torch, cwth, synth, dev, scales, args):
                                                                  row["hbm_frac"]))
 
 
+def dwt_bench(torch, cwth, synth, dev, scales, args):
+    """The DWT scalogram (Sec. II-A, Fig. 1c) of 10 s clips at 16 kHz with db4
+    and 14 levels (the deepest whose input still spans the 8 taps), for the
+    3-clip batch of the transform workload and a 256-clip batch: device time
+    per batch, the HBM rate of the whole call (algorithmic bytes: the signal
+    read once, the level record and the 14 x 160000 matrix written once), and
+    the CWTH of the same 3 clips (128 scales, BF16) at hops 1 and 512 beside it."""
+    h = cwth.daubechies(4)
+    levels = 14
+    stream = torch.cuda.current_stream()
+    plen = cwth.dwt_pyramid_length(N, levels)
+    for clips in [int(c) for c in args.dwt_clips.split(",")]:
+        xs = torch.from_numpy(np.stack([synth.make_clip(synth.clip_seed(2, 80 + (c % 16)), N, FS, 0.0)
+                                        for c in range(clips)])).to(dev)
+        pyr = torch.empty((clips, plen), dtype=torch.float32, device=dev)
+        out = torch.empty((clips, levels, N), dtype=torch.float32, device=dev)
+        run = lambda s_: cwth.dwt_scalogram(xs, h, levels, out=out, pyramid=pyr, stream=stream)
+        _, per = time_launches(torch, run, 1, max(args.steps, 20), args.warmup)
+        ms = float(np.mean(per))
+        byt = 4.0 * clips * (N + plen + levels * N)
+        row = {"clips": clips, "samples": N, "wavelet": "db4", "levels": levels, "us_per_batch": 1e3 * ms,
+               "matrix_entries_per_s": clips * levels * N / (ms * 1e-3), "alg_bytes": byt,
+               "gb_per_s": byt / (ms * 1e-3) / 1e9, "hbm_frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if clips == 3:
+            for hop in (1, 512):
+                plan = cwth.Plan(FS, scales, hop, "bf16")
+                ws = [plan(xs[c]) for c in range(clips)]
+                go = lambda s_: [plan.execute(xs[c], ws[c], stream) for c in range(clips)]
+                _, per_c = time_launches(torch, go, 1, max(args.steps, 20), args.warmup)
+                row["cwth_hop%d_us" % hop] = 1e3 * float(np.mean(per_c))
+        print(json.dumps({"metric": "DWT scalogram (filter bank, 14 levels, matrix)", **row}), flush=True)
+        log("dwt %d clips: %.1f us, %.0f GB/s (%.2f of HBM)%s" % (
+            clips, row["us_per_batch"], row["gb_per_s"], row["hbm_frac"],
+            "; cwth hop 1 %.1f us, hop 512 %.1f us" % (row["cwth_hop1_us"], row["cwth_hop512_us"])
+            if clips == 3 else ""))
+        del xs, pyr, out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -262,6 +303,9 @@ def main():
         return
     if args.image:
         image_bench(torch, cwth, synth, dev, scales, args)
+        return
+    if args.dwt:
+        dwt_bench(torch, cwth, synth, dev, scales, args)
         return
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame

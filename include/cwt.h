@@ -230,6 +230,45 @@ cwt_status cwt_scalogram_image(const float* scalogram, int32_t n_scales, int64_t
                                float* image, int32_t height, int32_t width, void* workspace,
                                void* stream);
 
+/* ------------------------------------------------------------------------
+ * DWT scalogram (Sec. II-A, Fig. 1c): the dyadic transform, scale 2^j and
+ * translation n 2^j at level j, computed by a two-channel filter bank with
+ * down-sampling by two, its detail coefficients spread back over the time
+ * axis to form a matrix.  With a_0 = x, len_0 = len, len_j = ceil(len_{j-1}/2):
+ *
+ *   a_j[n] = sum_k h[k] a_{j-1}[c(2n + k)],   d_j[n] = sum_k g[k] a_{j-1}[c(2n + k)]
+ *   g[k]   = (-1)^k h[h_len - 1 - k]
+ *   c(i)   = min(i mod P, len_{j-1} - 1),   P = len_{j-1} rounded up to even
+ *   S[j-1][t] = |d_j[t >> j]|,  t = 0 .. len - 1,  j = 1 .. levels
+ *
+ * (periodic extension; a level of odd length first repeats its last sample).
+ */
+
+/* Lowpass Daubechies filter with `order` vanishing moments (host, FP64):
+ * 2*order taps, sum sqrt(2), orthonormal under shifts by two, minimum phase;
+ * h_out[0] is the tap of the smallest delay.  h_out: host double[2*order].
+ * Errors: CWT_ERR_INVALID_ARG (order outside 1 .. 10, NULL h_out). */
+cwt_status cwt_daubechies(int32_t order, double* h_out);
+
+/* Floats per clip of the level record: 2 * sum_{j=1}^{levels} ceil(len / 2^j).
+ * -1 if len < 1 or levels outside 1 .. 30. */
+int64_t cwt_dwt_pyramid_length(int64_t len, int32_t levels);
+
+/*
+ * x: device float32[clips][len]; h: host double[h_len] (h_len even, 2 .. 64,
+ * any filter; rounded to FP32, g derived as above); pyramid: device
+ * float32[clips][cwt_dwt_pyramid_length(len, levels)], per level j = 1 ..
+ * levels a_j then d_j (ceil(len/2^j) each), written (it is also the
+ * intermediate between levels); out: device float32[clips][levels][len], the
+ * matrix S, or NULL to skip it.  All buffers owned by the caller.  FP32:
+ * every coefficient is an FMA chain over k in ascending order.  Asynchronous
+ * on `stream`.  Errors: CWT_ERR_INVALID_ARG (len outside 1 .. 2^31 - 1, clips
+ * outside 1 .. 65535, levels outside 1 .. 30, bad h_len, non-finite taps,
+ * NULL x, h or pyramid), CWT_ERR_DEVICE (launch failure).
+ */
+cwt_status cwt_dwt_scalogram(const float* x, int64_t len, int32_t clips, const double* h, int32_t h_len,
+                             int32_t levels, float* pyramid, float* out, void* stream);
+
 const char* cwt_status_string(cwt_status s);
 const char* cwt_last_error(void);
 

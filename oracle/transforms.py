@@ -1,7 +1,7 @@
 """FP64 CPU oracle for the steps next to the hop-strided CWT: decimation
 (the decimate-then-transform reading of the paper's workflow, Sec. III-B),
 the scalogram-to-image step (Sec. II-A, Fig. 1 and Sec. III-B: scalograms
-become CNN input images) and the DWT scalogram (Sec. II-C, Fig. 1c).
+become CNN input images) and the DWT scalogram (Sec. II-A, Fig. 1c).
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite and the benchmark's
 baseline legs, never by the library; it shares no code with it.  Plain numpy
@@ -114,3 +114,84 @@ def scalogram_image(w, amin: float, height: int, width: int) -> np.ndarray:
     if hi == lo:
         return np.zeros_like(b)
     return (b - lo) / (hi - lo)
+
+
+# ---------------------------------------------------------------------------
+# DWT scalogram (Sec. II-A, Fig. 1c: the dyadic transform computed by a filter
+# bank with down-sampling, its coefficients spread back over the time axis to
+# form a scale-by-time matrix).  Readings: orthogonal Daubechies filters dbN
+# (2N taps); periodic extension at every level, where a level of odd length is
+# first made even by repeating its last sample; filters applied in correlation
+# form a'[n] = sum_k h[k] a[(2n + k) mod P], d'[n] likewise with the mirror
+# filter g; matrix row j (level j = 1 is the finest) holds |d_j[t >> j]| for
+# t < N, i.e. each coefficient repeated over the 2^j samples it covers.
+
+def daubechies(order: int) -> np.ndarray:
+    """Lowpass dbN (2N taps, sum = sqrt(2)) by spectral factorisation: the
+    roots y_i of P(y) = sum_{k<N} C(N-1+k, k) y^k map through
+    z + 1/z = 2 - 4y to the roots z_i inside the unit circle, and
+    H(w) = sqrt(2) ((1 + w)/2)^N prod (w - z_i)/(1 - z_i), w = z^-1."""
+    order = int(order)
+    if order < 1:
+        raise ValueError("order >= 1")
+    p = [math.comb(order - 1 + k, k) for k in range(order)]        # ascending in y
+    ys = np.roots(p[::-1]) if order > 1 else np.array([])
+    zs = []
+    for y in ys:
+        b = 2.0 - 4.0 * y
+        disc = np.sqrt(b * b - 4.0 + 0j)
+        z1, z2 = (b + disc) / 2.0, (b - disc) / 2.0
+        zs.append(z1 if abs(z1) < 1.0 else z2)
+    q = np.poly(zs)[::-1] if zs else np.array([1.0 + 0j])            # ascending in w
+    q = q / np.prod([1.0 - z for z in zs]) if zs else q
+    binom = np.array([math.comb(order, k) for k in range(order + 1)], dtype=np.float64) / 2.0 ** order
+    h = math.sqrt(2.0) * np.convolve(binom, q.real)
+    return h
+
+
+def highpass(h) -> np.ndarray:
+    """g[k] = (-1)^k h[L-1-k] (quadrature mirror)."""
+    h = np.asarray(h, dtype=np.float64)
+    return np.array([(-1.0) ** k * h[len(h) - 1 - k] for k in range(len(h))])
+
+
+def dwt_level(a, h):
+    """One analysis step: returns (a', d), each of length ceil(len(a) / 2)."""
+    a = np.asarray(a, dtype=np.float64)
+    if len(a) % 2:
+        a = np.append(a, a[-1])
+    P = len(a)
+    g = highpass(h)
+    out_a, out_d = np.zeros(P // 2), np.zeros(P // 2)
+    for n in range(P // 2):
+        idx = [(2 * n + k) % P for k in range(len(h))]
+        out_a[n] = float(np.dot(h, a[idx]))
+        out_d[n] = float(np.dot(g, a[idx]))
+    return out_a, out_d
+
+
+def idwt_level(a, d, h, P: int):
+    """Inverse of one analysis step for an even period P (orthogonal filters)."""
+    g = highpass(h)
+    out = np.zeros(P)
+    for n in range(len(a)):
+        for k in range(len(h)):
+            out[(2 * n + k) % P] += h[k] * a[n] + g[k] * d[n]
+    return out
+
+
+def dwt(x, h, levels: int):
+    """[d_1, .., d_J], a_J."""
+    a, ds = np.asarray(x, dtype=np.float64), []
+    for _ in range(int(levels)):
+        a, d = dwt_level(a, h)
+        ds.append(d)
+    return ds, a
+
+
+def dwt_scalogram(x, h, levels: int) -> np.ndarray:
+    """S[j-1][t] = |d_j[t >> j]| for j = 1 .. levels, t < N."""
+    x = np.asarray(x, dtype=np.float64)
+    ds, _ = dwt(x, h, levels)
+    t = np.arange(len(x))
+    return np.stack([np.abs(d[t >> (j + 1)]) for j, d in enumerate(ds)])

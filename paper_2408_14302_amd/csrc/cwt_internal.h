@@ -130,6 +130,18 @@ int64_t image_workspace_bytes();
 hipError_t launch_image(const float* w, int n_scales, int64_t n_frames, float amin, float* image, int height,
                         int width, void* workspace, hipStream_t s);
 
+// DWT scalogram (dwt.hip): filter bank levels, then the scale-by-time matrix.
+constexpr int kDwtMaxTaps = 64;
+struct DwtFilter {      // analysis pair, FP32, passed by value as a kernel argument
+    float h[kDwtMaxTaps];
+    float g[kDwtMaxTaps];
+    int L;
+};
+// Floats per clip of the level record: per level j, a_j then d_j, ceil(len/2^j) each.
+int64_t dwt_pyramid_length(int64_t len, int J);
+hipError_t launch_dwt(const float* x, int64_t len, int clips, const DwtFilter& f, int J, float* pyramid,
+                      float* out, hipStream_t s);
+
 // Bank generation (bank.hip).
 struct BankScale {      // one sorted scale as the generator sees it
     double s;

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1263,6 +1264,118 @@ cwt_status cwt_decimate(const float* x, int64_t len, int32_t factor, const float
         if (st != CWT_OK) return st;
         HIP_TRY(launch_decimate(x, len, factor, h, h_len, y, (len + factor - 1) / factor, (hipStream_t)stream),
                 "decimate launch");
+        return CWT_OK;
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+// Daubechies lowpass filter of `order` vanishing moments by spectral
+// factorisation.  |H|^2 = cos^{2N}(w/2) P(sin^2(w/2)) with
+// P(y) = sum_{k<N} C(N-1+k, k) y^k; each root y of P gives the pair z, 1/z
+// with z + 1/z = 2 - 4y, and the minimum-phase factor keeps |z| < 1:
+// H(w) = sqrt(2) ((1 + w)/2)^N prod_i (w - z_i)/(1 - z_i), w = e^{-i omega}.
+// The roots of P come from Durand-Kerner iteration, polished by Newton steps.
+static void daubechies_taps(int N, double* h_out) {
+    using cd = std::complex<double>;
+    const int deg = N - 1;
+    std::vector<double> p(N);                     // ascending powers of y
+    for (int k = 0; k < N; ++k) {
+        double c = 1.0;                           // C(N-1+k, k)
+        for (int i = 1; i <= k; ++i) c = c * (N - 1 + i) / i;
+        p[k] = c;
+    }
+    auto peval = [&](cd y, cd* dp) {
+        cd v = 0.0, d = 0.0;
+        for (int k = deg; k >= 0; --k) {
+            d = d * y + v;
+            v = v * y + p[k];
+        }
+        if (dp) *dp = d;
+        return v;
+    };
+    std::vector<cd> y(deg);
+    for (int i = 0; i < deg; ++i) y[i] = std::pow(cd(0.4, 0.9), i);
+    for (int it = 0; it < 2000; ++it) {
+        double step = 0.0;
+        for (int i = 0; i < deg; ++i) {
+            cd den = p[deg];
+            for (int k = 0; k < deg; ++k)
+                if (k != i) den *= (y[i] - y[k]);
+            const cd dy = peval(y[i], nullptr) / den;
+            y[i] -= dy;
+            step = std::max(step, std::abs(dy) / std::max(1.0, std::abs(y[i])));
+        }
+        if (step < 1e-15) break;
+    }
+    for (int i = 0; i < deg; ++i)
+        for (int it = 0; it < 3; ++it) {
+            cd d;
+            const cd v = peval(y[i], &d);
+            if (std::abs(d) > 0.0) y[i] -= v / d;
+        }
+    std::vector<cd> q(1, cd(1.0));                // prod (w - z_i) / (1 - z_i), ascending in w
+    for (int i = 0; i < deg; ++i) {
+        const cd b = 2.0 - 4.0 * y[i];
+        const cd disc = std::sqrt(b * b - 4.0);
+        cd z = 0.5 * (b + disc);
+        if (std::abs(z) >= 1.0) z = 0.5 * (b - disc);
+        std::vector<cd> nq(q.size() + 1, cd(0.0));
+        for (size_t k = 0; k < q.size(); ++k) {
+            nq[k] -= z * q[k];
+            nq[k + 1] += q[k];
+        }
+        const cd scale = 1.0 / (1.0 - z);
+        for (auto& c : nq) c *= scale;
+        q.swap(nq);
+    }
+    std::vector<double> hb(N + 1);                // ((1 + w)/2)^N
+    for (int k = 0; k <= N; ++k) {
+        double c = 1.0;
+        for (int i = 1; i <= k; ++i) c = c * (N - k + i) / i;
+        hb[k] = std::ldexp(c, -N);
+    }
+    for (int k = 0; k < 2 * N; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i <= N; ++i) {
+            const int m = k - i;
+            if (m >= 0 && m < (int)q.size()) acc += hb[i] * q[m].real();
+        }
+        h_out[k] = std::sqrt(2.0) * acc;
+    }
+}
+
+cwt_status cwt_daubechies(int32_t order, double* h_out) {
+    if (order < 1 || order > 10) return fail(CWT_ERR_INVALID_ARG, "order must be in 1 .. 10");
+    if (!h_out) return fail(CWT_ERR_INVALID_ARG, "h_out is NULL");
+    daubechies_taps(order, h_out);
+    return CWT_OK;
+}
+
+int64_t cwt_dwt_pyramid_length(int64_t len, int32_t levels) {
+    if (len < 1 || levels < 1 || levels > 30) return -1;
+    return dwt_pyramid_length(len, levels);
+}
+
+cwt_status cwt_dwt_scalogram(const float* x, int64_t len, int32_t clips, const double* h, int32_t h_len,
+                             int32_t levels, float* pyramid, float* out, void* stream) {
+    try {
+        if (len < 1 || len > 0x7fffffffLL) return fail(CWT_ERR_INVALID_ARG, "len must be in 1 .. 2^31 - 1");
+        if (clips < 1 || clips > 65535) return fail(CWT_ERR_INVALID_ARG, "clips must be in 1 .. 65535");
+        if (levels < 1 || levels > 30) return fail(CWT_ERR_INVALID_ARG, "levels must be in 1 .. 30");
+        if (h_len < 2 || h_len > kDwtMaxTaps || h_len % 2) return fail(CWT_ERR_INVALID_ARG, "h_len must be even, 2 .. 64");
+        if (!x || !h || !pyramid) return fail(CWT_ERR_INVALID_ARG, "NULL x, h or pyramid");
+        DwtFilter f{};
+        f.L = h_len;
+        for (int k = 0; k < h_len; ++k) {
+            if (!std::isfinite(h[k])) return fail(CWT_ERR_INVALID_ARG, "non-finite filter tap");
+            f.h[k] = (float)h[k];
+            f.g[k] = (float)((k & 1) ? -h[h_len - 1 - k] : h[h_len - 1 - k]);
+        }
+        int dev = 0;
+        cwt_status st = current_device(&dev, nullptr);
+        if (st != CWT_OK) return st;
+        HIP_TRY(launch_dwt(x, len, clips, f, levels, pyramid, out, (hipStream_t)stream), "dwt launch");
         return CWT_OK;
     } catch (...) {
         return fail(CWT_ERR_INTERNAL, "unexpected exception");

@@ -47,6 +47,9 @@ _SIGS = {
     "cwt_decimated_length": (_i64, [_i64, _i32]),
     "cwt_lowpass_fir": (_i32, [_i32, _i32, _vp]),
     "cwt_decimate": (_i32, [_vp, _i64, _i32, _vp, _i32, _vp, _vp]),
+    "cwt_daubechies": (_i32, [_i32, _vp]),
+    "cwt_dwt_pyramid_length": (_i64, [_i64, _i32]),
+    "cwt_dwt_scalogram": (_i32, [_vp, _i64, _i32, _vp, _i32, _i32, _vp, _vp, _vp]),
     "cwt_status_string": (ctypes.c_char_p, [_i32]),
     "cwt_last_error": (ctypes.c_char_p, []),
     "cwt_version": (ctypes.c_char_p, []),
@@ -330,6 +333,56 @@ def scalogram_image(w, height: int, width: int, amin: float = 1e-6, out=None, wo
     _check(_lib.cwt_scalogram_image(w.data_ptr(), w.shape[0], w.shape[1], float(amin), out.data_ptr(), int(height),
                                     int(width), workspace.data_ptr(), _stream_ptr(stream)), "cwt_scalogram_image")
     return out
+
+
+def daubechies(order: int):
+    """Lowpass Daubechies filter, numpy float64[2*order] (cwt_daubechies)."""
+    h = np.empty(2 * int(order), dtype=np.float64)
+    _check(_lib.cwt_daubechies(int(order), h.ctypes.data_as(_vp)), "cwt_daubechies")
+    return h
+
+
+def dwt_pyramid_length(n: int, levels: int) -> int:
+    return int(_lib.cwt_dwt_pyramid_length(int(n), int(levels)))
+
+
+def dwt_levels(pyramid, n: int, levels: int):
+    """Views [(a_1, d_1), .., (a_J, d_J)] into a level record (last dim)."""
+    out, off = [], 0
+    for j in range(1, int(levels) + 1):
+        lj = (int(n) - 1 >> j) + 1
+        out.append((pyramid[..., off:off + lj], pyramid[..., off + lj:off + 2 * lj]))
+        off += 2 * lj
+    return out
+
+
+def dwt_scalogram(x, h, levels: int, out=None, pyramid=None, matrix: bool = True, stream=None):
+    """DWT scalogram on the device (cwt_dwt_scalogram).  x: contiguous float32
+    CUDA tensor [len] or [clips, len]; h: lowpass taps (host sequence, even
+    length).  Returns (S, pyramid): S is [levels, len] or [clips, levels, len]
+    (None when matrix is False), pyramid the per-level (a_j, d_j) record."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() in (1, 2)
+            and x.is_contiguous()):
+        raise TypeError("x must be a contiguous 1-D or 2-D float32 CUDA tensor")
+    hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(-1))
+    clips, n = (1, x.shape[0]) if x.dim() == 1 else (x.shape[0], x.shape[1])
+    plen = dwt_pyramid_length(n, levels)
+    if plen < 0 or clips < 1:
+        raise CwtError(INVALID_ARG, "cwt_dwt_scalogram")
+    lead = () if x.dim() == 1 else (clips,)
+    if pyramid is None:
+        pyramid = torch.empty(lead + (plen,), dtype=torch.float32, device=x.device)
+    elif pyramid.dtype != torch.float32 or not pyramid.is_contiguous() or pyramid.numel() != clips * plen:
+        raise ValueError("pyramid must be a contiguous float32 tensor of clips * dwt_pyramid_length elements")
+    if matrix and out is None:
+        out = torch.empty(lead + (int(levels), n), dtype=torch.float32, device=x.device)
+    elif matrix and (out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != clips * levels * n):
+        raise ValueError("out must be a contiguous float32 tensor of clips * levels * len elements")
+    _check(_lib.cwt_dwt_scalogram(x.data_ptr(), n, clips, hh.ctypes.data_as(_vp), hh.size, int(levels),
+                                  pyramid.data_ptr(), out.data_ptr() if matrix else None, _stream_ptr(stream)),
+           "cwt_dwt_scalogram")
+    return (out if matrix else None), pyramid
 
 
 def raw():
