@@ -201,6 +201,19 @@ def decimate_sweep(torch, cwth, synth, dev, scales, args):
             keep = torch.from_numpy(np.asarray(scales) >= 2 * hop).to(dev)   # scales resolved after decimation
             rel_res = float(d[keep].norm() / ref.double()[keep].norm()) if bool(keep.any()) else None
             row[name] = {"us": 1e3 * t, "rel_l2_vs_hop_strided": rel, "rel_l2_scales_ge_2hop": rel_res}
+        if not args.no_cpu:
+            import oracle
+            from oracle import transforms as T
+            xd = x.cpu().numpy().astype(np.float64)
+            hd = cwth.lowpass_fir(hop, 8 * hop + 1)
+            t0 = time.perf_counter()
+            oracle.cwt(xd, scales, hop)
+            t1 = time.perf_counter()
+            T.decimated_cwt(xd, scales, hop, hd)
+            t2 = time.perf_counter()
+            row["cpu_baseline"] = {"value": 1e6 * (t1 - t0), "unit": "us per clip (hop-strided)",
+                                   "fir_route_us": 1e6 * (t2 - t1), "cores": oracle.max_threads(), "kind": "oracle",
+                                   "sample": "the same clip, FP64: hop-strided transform and the FIR route"}
         print(json.dumps({"metric": "decimate-then-transform vs hop-strided transform, 10 s clip, 128 scales, bf16",
                           **row}), flush=True)
         log("hop %3d: strided %.1f us; decimate+cwt %.1f us (plain, dev %.3f / %s), %.1f us (fir, dev %.3f / %s)" % (
@@ -226,6 +239,13 @@ def image_bench(torch, cwth, synth, dev, scales, args):
         byt = 4.0 * w.numel() + 4.0 * 5 * 224 * 224
         row = {"hop": hop, "scalogram": list(w.shape), "image": [224, 224], "us_per_image": 1e3 * ms,
                "bytes": byt, "gb_per_s": byt / (ms * 1e-3) / 1e9, "hbm_frac": byt / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if not args.no_cpu:
+            from oracle import transforms as T
+            wd = w.cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            T.scalogram_image(wd, 1e-6, 224, 224)
+            row["cpu_baseline"] = {"value": 1e6 * (time.perf_counter() - t0), "unit": "us per image", "cores": 1,
+                                   "kind": "oracle", "sample": "the same scalogram, FP64 numpy"}
         print(json.dumps({"metric": "scalogram to image (dB, min-max, bilinear 224x224)", **row}), flush=True)
         log("image hop %d: %.1f us, %.0f GB/s (%.2f of HBM)" % (hop, row["us_per_image"], row["gb_per_s"],
                                                                  row["hbm_frac"]))
@@ -261,6 +281,14 @@ def dwt_bench(torch, cwth, synth, dev, scales, args):
                 go = lambda s_: [plan.execute(xs[c], ws[c], stream) for c in range(clips)]
                 _, per_c = time_launches(torch, go, 1, max(args.steps, 20), args.warmup)
                 row["cwth_hop%d_us" % hop] = 1e3 * float(np.mean(per_c))
+        if clips == 3 and not args.no_cpu:
+            from oracle import transforms as T
+            x0 = xs[0].cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            T.dwt_scalogram(x0, T.daubechies(4), levels)
+            sec = time.perf_counter() - t0
+            row["cpu_baseline"] = {"value": levels * N / sec, "unit": "matrix entries/s", "cores": 1, "kind": "oracle",
+                                   "seconds": sec, "sample": "one of the clips, FP64 numpy (a Python loop per level)"}
         print(json.dumps({"metric": "DWT scalogram (filter bank, 14 levels, matrix)", **row}), flush=True)
         log("dwt %d clips: %.1f us, %.0f GB/s (%.2f of HBM)%s" % (
             clips, row["us_per_batch"], row["gb_per_s"], row["hbm_frac"],

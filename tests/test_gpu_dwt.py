@@ -64,9 +64,11 @@ def _check_clip(cw, x, h, levels, S, pyr, label):
     print("%s: worst error / bound %.3f (deepest bound %.2e)" % (label, worst, bounds[-1]))
 
 
-CASES = [  # (n, order, levels): ragged lengths, both sides of the LDS tail (8192), deep levels of length 1
+CASES = [  # (n, order, levels): ragged lengths, both sides of the LDS tail (8192), deep levels of length 1,
+    # fused groups ending at the last level, and signals long enough for two fused groups
     (1, 1, 1), (2, 2, 3), (3, 4, 2), (7, 4, 5), (100, 2, 6), (1001, 10, 9), (8191, 4, 13), (8192, 4, 13),
-    (8193, 3, 14), (16385, 4, 12), (40000, 7, 15), (99999, 1, 17),
+    (8193, 3, 14), (16385, 4, 12), (40000, 7, 15), (70000, 10, 4), (99999, 1, 17), (270000, 2, 6),
+    (300001, 4, 9),
 ]
 
 
