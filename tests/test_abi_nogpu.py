@@ -94,3 +94,34 @@ def test_python_binding_refuses_without_device(lib):
     assert e.value.status == lib.DEVICE
     with pytest.raises(ValueError):
         lib.Plan(16000.0, [1.0], 4, "int8")
+
+
+def test_next_step_entry_points_without_device(lib):
+    # decimation, scalogram image and DWT: argument errors first, then the
+    # device error; host-only helpers work without a device
+    raw = lib.raw()
+    if _has_device(raw):
+        pytest.skip("a device is present")
+    fake = ctypes.c_void_p(0x1000)                     # never dereferenced: the calls stop before any launch
+    h1 = (ctypes.c_float * 1)(1.0)
+    assert raw.cwt_decimate(fake, 100, 0, h1, 1, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_decimate(fake, 100, 2, h1, 2, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_decimate(None, 100, 2, h1, 1, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_decimate(fake, 0, 2, h1, 1, fake, None) == lib.OK      # empty input is a no-op
+    assert raw.cwt_decimate(fake, 100, 2, h1, 1, fake, None) == lib.DEVICE
+    assert raw.cwt_image_workspace_bytes() > 0
+    assert raw.cwt_scalogram_image(fake, 0, 10, ctypes.c_float(1e-6), fake, 4, 4, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_scalogram_image(fake, 4, 10, ctypes.c_float(0.0), fake, 4, 4, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_scalogram_image(fake, 4, 10, ctypes.c_float(1e-6), fake, 4, 4, None, None) == lib.INVALID_ARG
+    assert raw.cwt_scalogram_image(fake, 4, 10, ctypes.c_float(1e-6), fake, 4, 4, fake, None) == lib.DEVICE
+    hd = (ctypes.c_double * 8)()
+    assert raw.cwt_daubechies(4, hd) == lib.OK
+    assert abs(sum(hd) - 2 ** 0.5) < 1e-14
+    assert raw.cwt_dwt_pyramid_length(10, 3) == 20
+    assert raw.cwt_dwt_pyramid_length(0, 3) == -1
+    assert raw.cwt_dwt_scalogram(fake, 100, 1, hd, 8, 0, fake, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_dwt_scalogram(fake, 100, 1, hd, 7, 3, fake, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_dwt_scalogram(fake, 100, 0, hd, 8, 3, fake, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_dwt_scalogram(fake, 0, 1, hd, 8, 3, fake, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_dwt_scalogram(fake, 100, 1, hd, 8, 3, None, fake, None) == lib.INVALID_ARG
+    assert raw.cwt_dwt_scalogram(fake, 100, 1, hd, 8, 3, fake, None, None) == lib.DEVICE   # matrix optional
