@@ -301,7 +301,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         msg = ("bench.py measures one GPU: this build runs the transform on a single MI355X "
-               "(the work shards by clip with no collective; see DESIGN.md). Run with --gpus 1.")
+               "(the work shards by clip with no collective). Run with --gpus 1.")
         print(msg, file=sys.stderr)
         print(json.dumps({"metric": METRIC, "error": msg, "n_gpus": args.gpus}))
         sys.exit(2)
