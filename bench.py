@@ -300,7 +300,7 @@ def dwt_bench(torch, cwth, synth, dev, scales, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        msg = ("bench.py measures one GPU: this build runs the transform on a single MI355X "
+        msg = ("bench.py measures one GPU: the transform runs on a single MI355X "
                "(the work shards by clip with no collective). Run with --gpus 1.")
         print(msg, file=sys.stderr)
         print(json.dumps({"metric": METRIC, "error": msg, "n_gpus": args.gpus}))
