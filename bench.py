@@ -464,8 +464,21 @@ def main():
         sm["qps_offered"] = args.qps
         sm["budget_bytes"] = 4 << 30
         sm["slots"] = 3
-        line["serving"] = sm
         log("  serving: p50 %.3f ms p99 %.3f ms" % (sm.get("p50_ms", float("nan")), sm.get("p99_ms", float("nan"))))
+        # closed-loop saturation, then an open-loop session at half of it
+        sat, _ = serve.saturation_session(4000, sclips, plans, executor=ex)
+        sat_qps = len(sat.latencies_ms) / sat.wall_s
+        half = 0.5 * sat_qps
+        log("  saturation %.0f requests/s; session at %.0f QPS ..." % (sat_qps, half))
+        hs, _ = serve.serve_session(half, args.serve_seconds, sclips, plans, seed=1430403, executor=ex)
+        hm = hs.summary()
+        hm["qps_offered"] = half
+        sm["saturation_qps"] = sat_qps
+        sm["at_half_saturation"] = {k: hm[k] for k in ("qps_offered", "completed", "p50_ms", "p99_ms", "mean_ms",
+                                                       "max_ms", "coeffs_per_s") if k in hm}
+        line["serving"] = sm
+        log("  at half saturation: p50 %.3f ms p99 %.3f ms" % (hm.get("p50_ms", float("nan")),
+                                                                hm.get("p99_ms", float("nan"))))
 
     # ---------------- CPU baseline (FP64 oracle) ----------------
     if not args.no_cpu and not args.only:
@@ -477,9 +490,23 @@ def main():
         for x in xs:
             oracle.cwt(x, scales, 1)
         dt_s = time.perf_counter() - t
+        oracle.set_threads(1)
+        t = time.perf_counter()
+        oracle.cwt(xs[0], scales, 1)
+        one_s = time.perf_counter() - t
+        oracle.set_threads(cores)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         line["cpu_baseline"] = {"value": len(xs) * S * N / dt_s, "unit": "coeffs/s", "cores": cores,
                                 "kind": "oracle", "seconds": dt_s,
-                                "sample": "the full step: 3 clips x 160000 samples x 128 scales at hop 1, FP64"}
+                                "sample": "the full step: 3 clips x 160000 samples x 128 scales at hop 1, FP64",
+                                "one_core": {"value": S * N / one_s, "seconds": one_s,
+                                             "sample": "one of the clips on one thread"},
+                                "cpu_model": model}
     print(json.dumps(line), flush=True)
 
 

@@ -234,6 +234,24 @@ def poisson_requests(seed: int, count: int, qps: float, clips: Sequence[Any], pl
     return out
 
 
+def saturation_session(count: int, clips, plans, scale_sets=(64, 128), hops=(1, 256, 512),
+                       budget_bytes: int = 4 << 30, slots: int = 3, max_batch: int = 64, seed: int = 1430402,
+                       executor: Optional[GpuExecutor] = None):
+    """Closed loop: `count` requests (the same random picks as a Poisson
+    session) all waiting at time 0, served as fast as admission allows.
+    completed / wall time is the saturation rate."""
+    import torch
+    reqs = poisson_requests(seed, count, 1.0, clips, plans, scale_sets, hops)
+    for r in reqs:
+        r.arrival = 0.0
+    ex = executor or GpuExecutor(slots, max_clips=max_batch)
+    sch = Scheduler(ex, budget_bytes, slots=slots, max_batch=max_batch)
+    torch.cuda.synchronize()
+    stats = sch.run(reqs)
+    torch.cuda.synchronize()
+    return stats, reqs
+
+
 def serve_session(qps: float, duration_s: float, clips, plans, scale_sets=(64, 128), hops=(1, 256, 512),
                   budget_bytes: int = 4 << 30, slots: int = 3, max_batch: int = 64, seed: int = 1430400,
                   keep_outputs: bool = False, executor: Optional[GpuExecutor] = None):

@@ -40,3 +40,15 @@ def test_budget_and_rejection_on_gpu():
     assert sm["max_inflight_bytes"] <= 4 << 20
     assert sm["rejected"] == sum(1 for r in reqs if r.footprint > (4 << 20)) > 0
     assert sm["completed"] == len(reqs) - sm["rejected"]
+
+
+def test_closed_loop_saturation_serves_every_request():
+    torch = torch_cuda()
+    from paper_2408_14302_amd import cwth, serve
+    clips = [torch.from_numpy(synth.make_clip(970 + i, 16000 * (1 + i), 16000.0, 0.0)).cuda() for i in range(4)]
+    plans = {(s, h): cwth.Plan(16000.0, synth.linear_scales(s), h, "bf16") for s in (64, 128) for h in (1, 256, 512)}
+    stats, reqs = serve.saturation_session(200, clips, plans, max_batch=16)
+    sm = stats.summary()
+    print(sm, "saturation %.0f requests/s" % (sm["completed"] / sm["wall_s"]))
+    assert sm["completed"] == len(reqs) == 200 and sm["rejected"] == 0
+    assert sm["max_concurrent_batches"] >= 2          # a backlog keeps several batches in flight
