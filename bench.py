@@ -88,6 +88,9 @@ def parse():
                     help="scalogram-to-image step (dB, min-max, bilinear to 224x224) timing (JSON lines)")
     ap.add_argument("--dwt", action="store_true",
                     help="DWT scalogram (db4, 14 levels) on 3 and 256 clips of 10 s, against the CWTH (JSON lines)")
+    ap.add_argument("--long", action="store_true",
+                    help="8 channels x 60 s at 48 kHz, 256 geometric scales 1..1024, hops 128 and 512, "
+                         "BF16 / FP8 / FP32 (JSON lines)")
     ap.add_argument("--dwt-clips", default="3,256", help="batch sizes for --dwt (comma separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
@@ -251,6 +254,45 @@ def image_bench(torch, cwth, synth, dev, scales, args):
                                                                  row["hbm_frac"]))
 
 
+def long_bench(torch, cwth, synth, dev, args):
+    """Long multichannel recordings: 8 channels x 60 s at 48 kHz (2,880,000
+    samples each), 256 geometric scales from 1 to 1024 samples, hops 128 and
+    512, all channels in one persistent launch (prepared batch, graph replay,
+    two input/output sets in alternation).  Reports coefficients/s, the
+    algorithmic TFLOP/s and its fraction of the dtype's dense peak (BF16
+    2.5 PFLOP/s, FP8 5.0, FP32 VALU 157.3 TFLOP/s), and FP8 and BF16 over FP32."""
+    n, fs, ch = 2880000, 48000.0, 8
+    scales = synth.geometric_scales(256, 1024.0)
+    flop_per_frame = float(alg_flops_per_coeff(scales).sum())
+    base = [torch.from_numpy(synth.make_clip(synth.clip_seed(5, c), n, fs, 0.0)).to(dev) for c in range(ch)]
+    stream = torch.cuda.current_stream()
+    peaks = {"bf16": PEAK_BF16_TFLOPS, "fp8": 2 * PEAK_BF16_TFLOPS, "fp32": 157.3}
+    for hop in (128, 512):
+        K = -(-n // hop)
+        row = {"hop": hop, "channels": ch, "samples": n, "scales": 256, "frames": K}
+        for dt in ("bf16", "fp8", "fp32"):
+            plan = cwth.Plan(fs, scales, hop, dt)
+            B = cwth.Batch(ch)
+            sets = [base, [b.clone() for b in base]]
+            outs = [[torch.empty((256, K), dtype=torch.float32, device=dev) for _ in range(ch)] for _ in range(2)]
+            prep = [B.prepare([plan] * ch, sets[j], outs[j]) for j in range(2)]
+            steps = max(3, min(args.steps, 20 if dt != "fp32" else 3))
+            _, per = time_launches(torch, lambda s_: prep[s_ % 2].run(stream=stream.cuda_stream, graph=True), 2,
+                                   steps, min(args.warmup, 2))
+            ms = float(np.mean(per))
+            tflops = flop_per_frame * K * ch / (ms * 1e-3) / 1e12
+            row[dt] = {"ms_per_launch": ms, "coeffs_per_s": ch * 256 * K / (ms * 1e-3), "tflops": tflops,
+                       "frac_of_peak": tflops / peaks[dt], "config": plan.config}
+            del prep, outs, B, plan
+        row["bf16_over_fp32"] = row["fp32"]["ms_per_launch"] / row["bf16"]["ms_per_launch"]
+        row["fp8_over_bf16"] = row["bf16"]["ms_per_launch"] / row["fp8"]["ms_per_launch"]
+        print(json.dumps({"metric": "8 x 60 s at 48 kHz, 256 geometric scales", **row}), flush=True)
+        log("hop %d: bf16 %.2f ms (%.0f TFLOP/s, %.2f of peak), fp8 %.2f ms (%.2f), fp32 %.1f ms; bf16/fp32 %.1f" % (
+            hop, row["bf16"]["ms_per_launch"], row["bf16"]["tflops"], row["bf16"]["frac_of_peak"],
+            row["fp8"]["ms_per_launch"], row["fp8"]["frac_of_peak"], row["fp32"]["ms_per_launch"],
+            row["bf16_over_fp32"]))
+
+
 def dwt_bench(torch, cwth, synth, dev, scales, args):
     """The DWT scalogram (Sec. II-A, Fig. 1c) of 10 s clips at 16 kHz with db4
     and 14 levels (the deepest whose input still spans the 8 taps), for the
@@ -334,6 +376,9 @@ def main():
         return
     if args.dwt:
         dwt_bench(torch, cwth, synth, dev, scales, args)
+        return
+    if args.long:
+        long_bench(torch, cwth, synth, dev, args)
         return
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame

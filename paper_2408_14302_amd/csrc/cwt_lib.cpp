@@ -469,15 +469,28 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
 // clips): small hops share a 128-frame window between two pairs of waves,
 // each running a balanced pair of blocks ({0,3}, {1,2}); larger hops take
 // narrower frame tiles with one block per wave.  FP8 has one configuration.
-static int default_cfg(int dt, int hop) {
-    if (dt == DT_FP32) return 0;
-    if (dt == DT_FP8) return kFp8Cfg;
-    if (hop <= 4) return 6;
-    if (hop <= 8) return 4;
-    return 5;
-}
 
 static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c, int chunk);
+
+// Default tile configuration, from configuration sweeps on MI355X (batches of
+// 10 s clips with 128 linear scales, 8 x 60 s at 48 kHz with 256 geometric
+// scales up to 1024, 10 s clips with 64 geometric scales up to 256, hops 1 to
+// 512): two 32-frame blocks per wave in 128-frame tiles (configuration 6) up
+// to hop 128, where tap fragments reused over two frame blocks pay for the
+// longer window; one block per wave in 32-frame tiles (5) beyond, where the
+// window grows with the hop and staging it dominates.  Configuration 6 falls
+// back to 5 when only the latter stages its whole window in LDS.
+static int default_cfg(const cwt_plan_s* p, int hop) {
+    if (p->dt == DT_FP32) return 0;
+    if (p->dt == DT_FP8) return kFp8Cfg;
+    if (hop > 128) return 5;
+    const MfmaCfg& c6 = kMfmaCfgs[6];
+    const MfmaCfg& c5 = kMfmaCfgs[5];
+    if (clip_layout(p->dt, *p->bank, hop, c6, c6.chunk).s.mode != STAGE_WIN &&
+        clip_layout(p->dt, *p->bank, hop, c5, c5.chunk).s.mode == STAGE_WIN)
+        return 5;
+    return 6;
+}
 
 static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     if (p->dt == DT_FP32) return cfg == 0;
@@ -1007,7 +1020,7 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
             std::call_once(attr_once, [&] { ae = mfma_init_attributes(); });
             if (ae != hipSuccess) return fail(CWT_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(ae));
         }
-        set_cfg(p.get(), default_cfg(p->dt, hop));
+        set_cfg(p.get(), default_cfg(p.get(), hop));
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto m = read_tune_cache();
