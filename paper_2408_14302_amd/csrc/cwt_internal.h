@@ -16,7 +16,7 @@ constexpr int kBlockRows = 32;     // scales per MFMA block (the M side of 32x32
 constexpr int kWaveSize = 64;
 constexpr int kMfmaWaves = 4;      // waves per MFMA work-group (split along frames)
 constexpr int kDirectFrames = 64;  // frames per direct-sum work-group (one per lane)
-constexpr int kDirectRows = 4;     // scales per direct-sum wave
+constexpr int kDirectRows = 16;    // scales per direct-sum wave
 constexpr int kDirectWaves = 4;    // waves per direct-sum work-group
 constexpr int kDirectChunk = 128;  // taps staged per LDS chunk in the direct kernel
 

@@ -2,8 +2,9 @@
 //
 //     W[i][k] = sum_{m=-M_i}^{M_i} t_i[m] * x~[k*hop + m]     (Eq. (1), Sec. II-A/II-B)
 //
-// Work-group tile: 64 consecutive frames (one per lane) x 16 sorted scales (four
-// waves, four scales each).  The taps of a wave's four scales are wave-uniform
+// Work-group tile: 64 consecutive frames (one per lane) x 64 sorted scales (four
+// waves, sixteen scales each: sixteen FMAs per signal value read from LDS and
+// per scalar load of a tap row).  The taps of a wave's scales are wave-uniform
 // and come through the scalar cache; the signal is staged in LDS in chunks of
 // kDirectChunk taps as X[c][f] = x~[(k0+f)*hop + m_c + c] (row stride 65 floats,
 // so both the staging writes and the per-lane reads are bank-conflict free for
@@ -57,6 +58,7 @@ __device__ __forceinline__ void direct_tile(const DirectArgs& a, const ClipArg& 
         __syncthreads();
         if (!active) continue;
         const int m_lo = max(mc, -P), m_hi = min(mc + kDirectChunk - 1, P);
+#pragma unroll 4
         for (int m = m_lo; m <= m_hi; ++m) {
             const float xv = X[(m - mc) * kRowStride + lane];
             const float* tp = taps + (int64_t)(m + P) * kDirectRows;
