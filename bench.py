@@ -159,6 +159,14 @@ def hop_sweep(torch, cwth, synth, dev, scales, args):
                        "roof_frac": max(t_flop, t_hbm) / (ms * 1e-3)}
             del prep, sets, outs, B, plan
         row["ratio_bf16_over_fp32"] = row["bf16"]["coeffs_per_s"] / row["fp32"]["coeffs_per_s"]
+        if not args.no_cpu:
+            import oracle
+            x0 = base[0].cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.cwt(x0, scales, hop)
+            sec = time.perf_counter() - t0
+            row["cpu_baseline"] = {"value": S * K / sec, "unit": "coeffs/s", "cores": oracle.max_threads(),
+                                   "kind": "oracle", "seconds": sec, "sample": "one of the clips, FP64"}
         print(json.dumps({"metric": "hop sweep: " + METRIC, **row}), flush=True)
         log("hop %4d: bf16 %.3e coeffs/s (%.1f us/clip, %.2f of %s roof), fp32 %.3e, ratio %.1f" % (
             hop, row["bf16"]["coeffs_per_s"], row["bf16"]["us_per_clip"], row["bf16"]["roof_frac"],
@@ -286,6 +294,14 @@ def long_bench(torch, cwth, synth, dev, args):
             del prep, outs, B, plan
         row["bf16_over_fp32"] = row["fp32"]["ms_per_launch"] / row["bf16"]["ms_per_launch"]
         row["fp8_over_bf16"] = row["bf16"]["ms_per_launch"] / row["fp8"]["ms_per_launch"]
+        if not args.no_cpu:
+            import oracle
+            x0 = base[0].cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.cwt(x0, scales, hop)
+            sec = time.perf_counter() - t0
+            row["cpu_baseline"] = {"value": 256 * K / sec, "unit": "coeffs/s", "cores": oracle.max_threads(),
+                                   "kind": "oracle", "seconds": sec, "sample": "one of the channels, FP64"}
         print(json.dumps({"metric": "8 x 60 s at 48 kHz, 256 geometric scales", **row}), flush=True)
         log("hop %d: bf16 %.2f ms (%.0f TFLOP/s, %.2f of peak), fp8 %.2f ms (%.2f), fp32 %.1f ms; bf16/fp32 %.1f" % (
             hop, row["bf16"]["ms_per_launch"], row["bf16"]["tflops"], row["bf16"]["frac_of_peak"],
