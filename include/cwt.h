@@ -151,8 +151,12 @@ cwt_status cwt_batch_execute(cwt_batch_t batch, const cwt_plan_t* plans,
  */
 cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out);
 
-/* Kernel configuration in use (index into the plan's candidate list) and the
- * number of candidates; a forced choice (for tests) via cwt_plan_set_config. */
+/* Kernel configuration of the plan (index into the candidate list) and the
+ * number of candidates; a forced choice via cwt_plan_set_config.  A plan left
+ * at its default configuration (neither set nor tuned) may run a launch with
+ * few frames under a smaller-tile candidate instead (BF16, FP16 and BF16x3
+ * results do not depend on the configuration); a set or tuned configuration
+ * is used for every launch. */
 int32_t cwt_plan_config(cwt_plan_t plan);
 int32_t cwt_plan_num_configs(cwt_plan_t plan);
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
