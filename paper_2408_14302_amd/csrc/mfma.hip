@@ -674,6 +674,42 @@ __device__ __forceinline__ void tile_loop_linear(const MfmaArgs& a, const ClipAr
 // slot (w + tile) % WB (rotated so that the widest block of a group does not
 // always land on the same SIMD).  All waves share the staged rows; each wave
 // runs only the K-steps of its own block.
+// The lane's 16 output rows of a block (and the FP8 descale factors), loaded
+// together so that the epilogue's stores wait on at most one memory round
+// trip.  Loaded one per store instead, each load was waited for with every
+// earlier store still in flight (loads and stores complete in order), which
+// serialised the epilogue: it took about as long as the block's K loop.
+template <int DT>
+struct RowMap {
+    int row[16];
+    float scale[DT == DT_FP8 ? 16 : 1];
+};
+
+template <int DT>
+__device__ __forceinline__ void load_rows(const MfmaBlock* __restrict__ B, int hg, RowMap<DT>& m) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
+        m.row[v] = B->rows[rr];
+        if constexpr (DT == DT_FP8) m.scale[v] = B->inv_alpha[rr];
+    }
+}
+
+// Epilogue of one 32x32 accumulator: FP8 descale, |.| unless signed output,
+// non-temporal stores of the lane's column k.
+template <int DT>
+__device__ __forceinline__ void store_rows(const RowMap<DT>& m, const f32x16& acc, float inv_beta, int signed_out,
+                                           float* out, int64_t K, int64_t k) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        if (m.row[v] < 0) continue;
+        float val = acc[v];
+        if constexpr (DT == DT_FP8) val = val * (m.scale[v] * inv_beta);
+        if (!signed_out) val = fabsf(val);
+        __builtin_nontemporal_store(val, out + (int64_t)m.row[v] * K + k);
+    }
+}
+
 template <int DT>
 __device__ __forceinline__ void process_tile_split(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
                                                    uint8_t* lds, float* red) {
@@ -736,16 +772,9 @@ __device__ __forceinline__ void process_tile_split(const MfmaArgs& a, const Clip
     const float inv_beta = 1.0f / beta;
     const int64_t k = k0 + 32 * wf + n;
     if (k >= c.K) return;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
-        const int row = B->rows[rr];
-        if (row < 0) continue;
-        float val = acc[0][v];
-        if constexpr (DT == DT_FP8) val = val * (B->inv_alpha[rr] * inv_beta);
-        if (!a.signed_out) val = fabsf(val);
-        __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
-    }
+    RowMap<DT> rm;
+    load_rows<DT>(B, hg, rm);
+    store_rows<DT>(rm, acc[0], inv_beta, a.signed_out, c.out, c.K, k);
 }
 
 // LINEAR work-group tile: F = 128*A consecutive frames of one clip against one
@@ -781,20 +810,13 @@ __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c
 
     // Epilogue: optional descale (FP8), |.| unless signed output, coalesced store.
     const float inv_beta = 1.0f / beta;
+    RowMap<DT> rm;
+    load_rows<DT>(B, hg, rm);
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
         const int64_t k = k0 + 32 * (A * w + fa) + n;
         if (k >= c.K) continue;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
-            const int row = B->rows[rr];
-            if (row < 0) continue;
-            float val = acc[fa][v];
-            if constexpr (DT == DT_FP8) val = val * (B->inv_alpha[rr] * inv_beta);
-            if (!a.signed_out) val = fabsf(val);
-            __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
-        }
+        store_rows<DT>(rm, acc[fa], inv_beta, a.signed_out, c.out, c.K, k);
     }
 }
 
@@ -882,7 +904,7 @@ __device__ __forceinline__ int wave_block(int i, int ws, int WS, int WB, int til
 
 // K-steps, MFMAs and epilogue of one block for the wave's A frame blocks
 // (fb0 ..); ta/tb hold the block's first eight tap fragments on entry.
-template <int DT, int A>
+template <int DT, int A, bool EARLY>
 __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, const Geo& g, const uint8_t* lds,
                                           const MfmaBlock* __restrict__ B, int glo, int64_t k0, int fb0,
                                           float inv_beta, Frag<DT> (&ta)[4], Frag<DT> (&tb)[4]) {
@@ -895,6 +917,8 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
     for (int fa = 0; fa < A; ++fa)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
+    RowMap<DT> rm;
+    if constexpr (EARLY) load_rows<DT>(B, hg, rm);    // in flight during the K loop
     int base[A], unit0[A];
     if (g.swz >= 0) {
         lane_bases<DT, A, LM_LINEAR_SWZ>(c, g, fb0, base, unit0);
@@ -905,20 +929,12 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
         compute_chunk<DT, A, LM_LINEAR>(lds, g, 31, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase, ta, tb,
                                         acc);
     }
+    if constexpr (!EARLY) load_rows<DT>(B, hg, rm);   // where registers are short
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
         const int64_t k = k0 + 32 * (fb0 + fa) + n;
         if (k >= c.K) continue;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int rr = 8 * (v >> 2) + 4 * hg + (v & 3);
-            const int row = B->rows[rr];
-            if (row < 0) continue;
-            float val = acc[fa][v];
-            if constexpr (DT == DT_FP8) val = val * (B->inv_alpha[rr] * inv_beta);
-            if (!a.signed_out) val = fabsf(val);
-            __builtin_nontemporal_store(val, c.out + (int64_t)row * c.K + k);
-        }
+        store_rows<DT>(rm, acc[fa], inv_beta, a.signed_out, c.out, c.K, k);
     }
 }
 
@@ -927,7 +943,7 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
 // group w / WS (A frame blocks) and runs its share of the group's blocks
 // (wave_block) one after the other: the stores of one block drain while the
 // next one's MFMAs run.
-template <int DT, int A>
+template <int DT, int A, bool EARLY>
 __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
                                                  uint8_t* lds, float* red) {
     using T = Tr<DT>;
@@ -963,7 +979,7 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
     lds_barrier();
     for (int i = 0; j < nb; j = wave_block(++i, ws, WS, WB, tile)) {
         if (i > 0) prefetch(a.blocks + b0 + j);
-        win_block<DT, A>(a, c, g, lds, a.blocks + b0 + j, glo, k0, A * wf, inv_beta, ta, tb);
+        win_block<DT, A, EARLY>(a, c, g, lds, a.blocks + b0 + j, glo, k0, A * wf, inv_beta, ta, tb);
     }
 }
 
@@ -1005,7 +1021,8 @@ void k_mfma_win(MfmaArgs a) {
     if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
     const int ng = (a.ngroups + a.clip.wb - 1) / a.clip.wb;
     const int tile = id / ng, grp = id - tile * ng;
-    process_tile_win<DT, A>(a, a.clip, tile, grp, lds, red);
+    // the row map rides through the K loop only where the register budget has room
+    process_tile_win<DT, A, A == 2 && !WinOcc<DT, A>::wide>(a, a.clip, tile, grp, lds, red);
 }
 
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
@@ -1052,7 +1069,7 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
         {
             const int ng = (a.ngroups + c.wb - 1) / c.wb;
             const int tile = local / ng, grp = local - tile * ng;
-            process_tile_win<DT, A>(a, c, tile, grp, lds, red);
+            process_tile_win<DT, A, false>(a, c, tile, grp, lds, red);
         }
         lds_barrier();                          // LDS free for the next tile
     }
