@@ -103,6 +103,19 @@ def _check_signal(x):
         raise ValueError("x must be 1-D and contiguous")
 
 
+def _check_buffer(t, device, numel, name, dtype=None):
+    """A caller's output or workspace: a contiguous tensor of `numel` elements
+    of `dtype` (float32 by default) in the memory of `device` (the input's
+    GPU).  The library receives a bare pointer, so a host tensor or another
+    GPU's must be refused here."""
+    import torch
+    dtype = torch.float32 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device != device:
+        raise ValueError("%s must be a CUDA tensor on %s" % (name, device))
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError("%s must be a contiguous %s tensor of %d elements" % (name, dtype, numel))
+
+
 class Plan:
     """A resident plan: scales (samples), hop, operand dtype and output mode.
 
@@ -169,15 +182,19 @@ class Plan:
         return int(c.value)
 
     def output(self, n: int, device=None):
+        """An uninitialised [n_scales, K] float32 output on `device` (default:
+        the current GPU)."""
         import torch
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
         return torch.empty((self.num_scales, self.num_frames(n)), dtype=torch.float32, device=device)
 
     def execute(self, x, out, stream=None) -> None:
-        """Queue the transform of x into out (both CUDA tensors) on `stream`."""
+        """Queue the transform of x into out (both CUDA tensors on one device)
+        on `stream`."""
         _check_signal(x)
         n = x.numel()
-        if out.dtype.itemsize != 4 or not out.is_contiguous() or out.numel() != self.num_scales * self.num_frames(n):
-            raise ValueError("out must be a contiguous float32 tensor of n_scales * K elements")
+        _check_buffer(out, x.device, self.num_scales * self.num_frames(n), "out")
         _check(_lib.cwt_execute(self._h, x.data_ptr() if n else None, n, out.data_ptr() if n else None,
                                 _stream_ptr(stream)), "cwt_execute")
 
@@ -203,6 +220,8 @@ def _arrays(plans, xs, outs):
     n = len(plans)
     if not (len(xs) == len(outs) == n):
         raise ValueError("plans, xs and outs differ in length")
+    for i, (p, x, o) in enumerate(zip(plans, xs, outs)):
+        _check_buffer(o, x.device, p.num_scales * p.num_frames(x.numel()), "outs[%d]" % i)
     P = (_vp * n)(*[p.handle.value for p in plans])
     X = (_vp * n)(*[x.data_ptr() if x.numel() else None for x in xs])
     L = (_i64 * n)(*[x.numel() for x in xs])
@@ -302,17 +321,17 @@ def decimate(x, factor: int, h=None, out=None, stream=None):
     _check_signal(x)
     if h is None:
         h = torch.ones(1, dtype=torch.float32, device=x.device)
-    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float32 and h.dim() == 1
-            and h.is_contiguous()):
-        raise TypeError("h must be a contiguous 1-D float32 CUDA tensor")
+    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.device == x.device and h.dtype == torch.float32
+            and h.dim() == 1 and h.is_contiguous()):
+        raise TypeError("h must be a contiguous 1-D float32 tensor on the signal's GPU")
     n = x.numel()
     ny = decimated_length(n, factor)
     if ny < 0:
         raise CwtError(INVALID_ARG, "cwt_decimate")
     if out is None:
         out = torch.empty(ny, dtype=torch.float32, device=x.device)
-    elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != ny:
-        raise ValueError("out must be a contiguous float32 tensor of ceil(len / factor) elements")
+    else:
+        _check_buffer(out, x.device, ny, "out")
     _check(_lib.cwt_decimate(x.data_ptr() if n else None, n, int(factor), h.data_ptr(), h.numel(),
                              out.data_ptr() if n else None, _stream_ptr(stream)), "cwt_decimate")
     return out
@@ -326,10 +345,17 @@ def scalogram_image(w, height: int, width: int, amin: float = 1e-6, out=None, wo
     if not (isinstance(w, torch.Tensor) and w.is_cuda and w.dtype == torch.float32 and w.dim() == 2
             and w.is_contiguous()):
         raise TypeError("w must be a contiguous 2-D float32 CUDA tensor")
+    if int(height) < 1 or int(width) < 1:
+        raise CwtError(INVALID_ARG, "cwt_scalogram_image")
+    ws_bytes = int(_lib.cwt_image_workspace_bytes())
     if out is None:
         out = torch.empty((int(height), int(width)), dtype=torch.float32, device=w.device)
+    else:
+        _check_buffer(out, w.device, int(height) * int(width), "out")
     if workspace is None:
-        workspace = torch.empty(int(_lib.cwt_image_workspace_bytes()), dtype=torch.uint8, device=w.device)
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=w.device)
+    else:
+        _check_buffer(workspace, w.device, ws_bytes, "workspace", torch.uint8)
     _check(_lib.cwt_scalogram_image(w.data_ptr(), w.shape[0], w.shape[1], float(amin), out.data_ptr(), int(height),
                                     int(width), workspace.data_ptr(), _stream_ptr(stream)), "cwt_scalogram_image")
     return out
@@ -373,12 +399,12 @@ def dwt_scalogram(x, h, levels: int, out=None, pyramid=None, matrix: bool = True
     lead = () if x.dim() == 1 else (clips,)
     if pyramid is None:
         pyramid = torch.empty(lead + (plen,), dtype=torch.float32, device=x.device)
-    elif pyramid.dtype != torch.float32 or not pyramid.is_contiguous() or pyramid.numel() != clips * plen:
-        raise ValueError("pyramid must be a contiguous float32 tensor of clips * dwt_pyramid_length elements")
+    else:
+        _check_buffer(pyramid, x.device, clips * plen, "pyramid")
     if matrix and out is None:
         out = torch.empty(lead + (int(levels), n), dtype=torch.float32, device=x.device)
-    elif matrix and (out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != clips * levels * n):
-        raise ValueError("out must be a contiguous float32 tensor of clips * levels * len elements")
+    elif matrix:
+        _check_buffer(out, x.device, clips * int(levels) * n, "out")
     _check(_lib.cwt_dwt_scalogram(x.data_ptr(), n, clips, hh.ctypes.data_as(_vp), hh.size, int(levels),
                                   pyramid.data_ptr(), out.data_ptr() if matrix else None, _stream_ptr(stream)),
            "cwt_dwt_scalogram")
