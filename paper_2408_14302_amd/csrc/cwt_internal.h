@@ -45,7 +45,8 @@ struct DirectGroup {
 // wave loads it with one coalesced access per lane.  BF16X3 stores the hi
 // fragment followed by the lo fragment.
 struct MfmaBlock {
-    int32_t lo, hi;        // K-step range; hi - lo + 1 is a multiple of 8 (zero-tap padding)
+    int32_t lo, hi;        // K-step range in whole groups of 8 (zero-tap padding), hi >= ehi + 3
+    int32_t elo, ehi;      // the steps that hold the block's taps: [elo, ehi] within [lo, hi]
     int64_t frag_off;      // byte offset of step `lo` in the fragment buffer
     int32_t rows[kBlockRows];
     float inv_alpha[kBlockRows]; // FP8 only: 1/alpha_r; 1 otherwise

@@ -336,14 +336,17 @@ static cwt_status build_bank(int dt, int device, const std::vector<double>& scal
                 B.inv_alpha[r] = p < S ? (float)(1.0 / alpha[p]) : 1.0f;
                 if (p < S) Mb = std::max(Mb, bk->M_sorted[p]);
             }
-            // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb]
-            // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb], widened to whole
-            // groups of eight steps aligned to multiples of 8 (the extra steps
-            // hold zero taps): the K loop then never ends inside a group, and
-            // any 8-aligned chunk meets every block on group boundaries
+            // steps ks with [KS*ks, KS*ks + KS) meeting [-Mb, Mb]: [elo, ehi].
+            // Stored widened to whole groups of eight steps aligned to
+            // multiples of 8 and reaching at least three steps past ehi (the
+            // extra steps hold zero taps): chunked tiles run the widened range,
+            // so any 8-aligned chunk meets every block on group boundaries; WIN
+            // tiles run [elo, ehi] rounded up to a multiple of four steps.
             const int lo0 = (int)std::floor(-(double)Mb / KS), hi0 = Mb / KS;
+            B.elo = lo0;
+            B.ehi = hi0;
             B.lo = (int)std::floor(lo0 / 8.0) * 8;
-            B.hi = (int)std::ceil((hi0 + 1) / 8.0) * 8 - 1;
+            B.hi = (int)std::ceil((hi0 + 4) / 8.0) * 8 - 1;
             B.frag_off = off;
             off += (int64_t)(B.hi - B.lo + 1) * step_bytes;
             bk->blocks.push_back(B);

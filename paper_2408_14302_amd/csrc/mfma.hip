@@ -580,7 +580,9 @@ constexpr int x_depth() { return A >= 4 ? 1 : 2; }
 // block's signal fragment (from LDS) for step j + XD is read into the
 // registers that step j's MFMA has just consumed.  Every register slot is a
 // compile-time constant.  LAST: the final group (no reads past its end).
-template <int DT, int A, int LM, int XD, bool LAST>
+// FRONT: a range that starts halfway into this group: steps 0-3 do nothing
+// (their slots already hold the taps of steps 8-11).
+template <int DT, int A, int LM, int XD, bool LAST, bool FRONT = false>
 __device__ __forceinline__ void step_group(const uint8_t* cur, const Geo& g, int swz, const int (&base)[A],
                                            const int (&unit0)[A], int dq, int s8, int hi, int lo,
                                            const uint8_t* __restrict__ tbase, Frag<DT> (&ta)[4], Frag<DT> (&tb)[4],
@@ -591,6 +593,7 @@ __device__ __forceinline__ void step_group(const uint8_t* cur, const Geo& g, int
     for (int j = 0; j < 8; ++j) {
         Frag<DT>& tcur = j < 4 ? ta[j & 3] : tb[j & 3];
         const bool next = !(LAST && j + XD > 7);
+        if (FRONT && j < 4) continue;
 #pragma unroll
         for (int fa = 0; fa < A; ++fa) {
             acc[fa] = mma_all<DT>(tcur, x[j % XD][fa], acc[fa]);
@@ -604,10 +607,14 @@ __device__ __forceinline__ void step_group(const uint8_t* cur, const Geo& g, int
     }
 }
 
-// The MFMAs of steps ks_c+d0 .. ks_c+d0+ns-1 (ns a multiple of 8) of the chunk
-// starting at ks_c, from LDS buffer `cur`; ta/tb hold the taps of the first
-// eight steps on entry.
-template <int DT, int A, int LM>
+// The MFMAs of steps ks_c+d0 .. ks_c+d0+ns-1 of the chunk starting at ks_c,
+// from LDS buffer `cur`.  ns is a multiple of 8, or with WHOLE of 4 (a
+// block's whole range, rounded up): then an odd half group comes first, as
+// the second half of a group that starts four steps early.  On entry ta/tb
+// hold the taps of the first eight steps (with an odd half first, tb holds
+// its four and ta the four after them); chunked tiles leave in them the taps
+// of the eight steps after the range.
+template <int DT, int A, int LM, bool WHOLE = false>
 __device__ __forceinline__ void compute_chunk(const uint8_t* cur, const Geo& g, int swz, const int (&base)[A],
                                               const int (&unit0)[A], int ks_c, int d0, int ns, int hi, int lo,
                                               const uint8_t* __restrict__ tbase, Frag<DT> (&ta)[4],
@@ -617,6 +624,12 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* cur, const Geo& g, 
 #pragma unroll
     for (int d = 0; d < XD; ++d) load_x<DT, A, LM>(cur, g.plane_bytes, swz, base, unit0, d0 + d, x[d]);
     int q = 0;
+    if (WHOLE && (ns & 4)) {
+        step_group<DT, A, LM, XD, false, true>(cur, g, swz, base, unit0, d0 - 4, ks_c + d0 - 4, hi, lo, tbase, ta, tb,
+                                               x, acc);
+        q = 4;
+        if (ns == 4) return;
+    }
     for (; q + 8 < ns; q += 8)
         step_group<DT, A, LM, XD, false>(cur, g, swz, base, unit0, d0 + q, ks_c + d0 + q, hi, lo, tbase, ta, tb, x,
                                          acc);
@@ -910,7 +923,7 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
                                           float inv_beta, Frag<DT> (&ta)[4], Frag<DT> (&tb)[4]) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 31, hg = lane >> 5;
-    const int lo = B->lo, hi = B->hi;
+    const int lo = B->lo, elo = B->elo, ns = (B->ehi - elo + 4) & ~3;   // steps, rounded up to four
     const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
     f32x16 acc[A];
 #pragma unroll
@@ -922,12 +935,12 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
     int base[A], unit0[A];
     if (g.swz >= 0) {
         lane_bases<DT, A, LM_LINEAR_SWZ>(c, g, fb0, base, unit0);
-        compute_chunk<DT, A, LM_LINEAR_SWZ>(lds, g, g.swz, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase,
-                                            ta, tb, acc);
+        compute_chunk<DT, A, LM_LINEAR_SWZ, true>(lds, g, g.swz, base, unit0, glo, elo - glo, ns, elo + ns - 1, lo,
+                                                  tbase, ta, tb, acc);
     } else {
         lane_bases<DT, A, LM_LINEAR>(c, g, fb0, base, unit0);
-        compute_chunk<DT, A, LM_LINEAR>(lds, g, 31, base, unit0, glo, lo - glo, hi - lo + 1, hi, lo, tbase, ta, tb,
-                                        acc);
+        compute_chunk<DT, A, LM_LINEAR, true>(lds, g, 31, base, unit0, glo, elo - glo, ns, elo + ns - 1, lo, tbase,
+                                              ta, tb, acc);
     }
     if constexpr (!EARLY) load_rows<DT>(B, hg, rm);   // where registers are short
 #pragma unroll
@@ -963,15 +976,18 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
     if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
     const float inv_beta = 1.0f / beta;
 
-    // taps of the first eight steps of the wave's first block
+    // taps of the first steps of the wave's first block (compute_chunk with
+    // WHOLE): elo <= 0 and hi >= 7, so steps elo .. elo+7 lie in the block's
+    // stored range (those past ehi hold zeros)
     int j = wave_block(0, ws, WS, WB, tile);
     Frag<DT> ta[4], tb[4];
     auto prefetch = [&](const MfmaBlock* __restrict__ B) {
-        const uint8_t* __restrict__ tbase = a.frags + B->frag_off;
+        const uint8_t* __restrict__ tbase = a.frags + B->frag_off + (int64_t)(B->elo - B->lo) * T::STEP;
+        const int front = ((B->ehi - B->elo + 4) & 4) ? 4 : 0;   // an odd half group comes first
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            load_tap<DT>(tbase + (int64_t)s * T::STEP, lane, ta[s]);
-            load_tap<DT>(tbase + (int64_t)(4 + s) * T::STEP, lane, tb[s]);
+            load_tap<DT>(tbase + (int64_t)(front + s) * T::STEP, lane, ta[s]);
+            load_tap<DT>(tbase + (int64_t)(4 - front + s) * T::STEP, lane, tb[s]);
         }
     };
     if (j < nb) prefetch(a.blocks + b0 + j);
