@@ -44,10 +44,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "fetch_kib": 1850.98, "write_kib": 80000.01,
-                  "src_sha256": "68927c615e76d88677ccb8c46907a1775bc70106c0f08993fb02c08a1c396252"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 1>", "fetch_kib": 97435.40, "write_kib": 57289.76,
-                    "src_sha256": "68927c615e76d88677ccb8c46907a1775bc70106c0f08993fb02c08a1c396252"},
+    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "fetch_kib": 1804.20, "write_kib": 80000.24,
+                  "src_sha256": "565088f8726c3831b4a1a8b2dd1ed08c22e95648ca5a5d6a092c4f2fd1331bf8"},
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 1>", "fetch_kib": 99151.80, "write_kib": 59338.56,
+                    "src_sha256": "565088f8726c3831b4a1a8b2dd1ed08c22e95648ca5a5d6a092c4f2fd1331bf8"},
 }
 
 

@@ -1091,8 +1091,17 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
     }
 }
 
+// The every-layout kernel holds the chunked and row tiles' state beside the
+// WIN tile's: two waves per SIMD for BF16/FP16 up to A = 2 (it serves mixed
+// batches such as a hop-1 request among larger hops), one otherwise.
 template <int DT, int A>
-__global__ __launch_bounds__(256) void k_mfma_persistent(MfmaArgs a) {
+struct AnyOcc {
+    static constexpr int W = (DT == DT_BF16 || DT == DT_FP16) && A <= 2 ? 2 : 1;
+};
+
+template <int DT, int A>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AnyOcc<DT, A>::W)))
+void k_mfma_persistent(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ float red[kMfmaWaves];
     __shared__ int spre[kPrefixLds];
