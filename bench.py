@@ -44,9 +44,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "fetch_kib": 1804.20, "write_kib": 80000.24,
+    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "config": 6, "fetch_kib": 1804.20, "write_kib": 80000.05,
                   "src_sha256": "565088f8726c3831b4a1a8b2dd1ed08c22e95648ca5a5d6a092c4f2fd1331bf8"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 1>", "fetch_kib": 99151.80, "write_kib": 59338.56,
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 86171.09,
+                    "write_kib": 55145.79,
                     "src_sha256": "565088f8726c3831b4a1a8b2dd1ed08c22e95648ca5a5d6a092c4f2fd1331bf8"},
 }
 
@@ -57,9 +58,11 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_bytes(leg):
+def traffic_bytes(leg, config):
+    """Counted HBM bytes per launch, while the kernel source and the launch's
+    tile configuration are the ones the counters were taken with."""
     rec = TRAFFIC.get(leg)
-    if not rec or rec["src_sha256"] != kernel_sha():
+    if not rec or rec["src_sha256"] != kernel_sha() or rec["config"] != config:
         return None
     return 1024.0 * (FETCH_SCALE * rec["fetch_kib"] + WRITE_SCALE * rec["write_kib"])
 
@@ -166,7 +169,7 @@ def hop_sweep(torch, cwth, synth, dev, scales, args):
             t_hbm = nb * (4.0 * N + 4.0 * S * K) / (PEAK_HBM_GBS * 1e9)
             bound = "mfma" if dt == "bf16" and t_flop >= t_hbm else ("hbm" if t_hbm >= t_flop else "valu")
             row[dt] = {"coeffs_per_s": coeffs / (ms * 1e-3), "us_per_clip": 1e3 * ms / nb, "ms_per_launch": ms,
-                       "config": plan.config, "bound": bound,
+                       "config": plan.launch_config(N, nb), "bound": bound,
                        "roof_frac": max(t_flop, t_hbm) / (ms * 1e-3)}
             del prep, sets, outs, B, plan
         row["ratio_bf16_over_fp32"] = row["bf16"]["coeffs_per_s"] / row["fp32"]["coeffs_per_s"]
@@ -305,7 +308,7 @@ def long_bench(torch, cwth, synth, dev, args):
             ms = float(np.mean(per))
             tflops = flop_per_frame * K * ch / (ms * 1e-3) / 1e12
             row[dt] = {"ms_per_launch": ms, "coeffs_per_s": ch * 256 * K / (ms * 1e-3), "tflops": tflops,
-                       "frac_of_peak": tflops / peaks[dt], "config": plan.config}
+                       "frac_of_peak": tflops / peaks[dt], "config": plan.launch_config(n, ch)}
             del prep, outs, B, plan
         row["bf16_over_fp32"] = row["fp32"]["ms_per_launch"] / row["bf16"]["ms_per_launch"]
         row["fp8_over_bf16"] = row["bf16"]["ms_per_launch"] / row["fp8"]["ms_per_launch"]
@@ -435,7 +438,7 @@ def main():
         # per-kernel duration: one launch per clip inside each step
         per_launch_ms = float(np.mean(per)) / len(clips)
         return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": per_launch_ms,
-                "steps": steps, "config": plan.config}
+                "steps": steps, "config": plan.launch_config(N, 1)}
 
     # hop 512: many clips per launch (one clip alone is ~0.1 us of work)
     nb = args.batch512
@@ -467,7 +470,7 @@ def main():
         coeffs = nb * S * K512
         return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": float(np.mean(per)),
                 "per_launch_ms_direct": float(np.mean(per_direct)), "clips_per_launch": nb, "steps": steps,
-                "config": plan.config}
+                "config": plan.launch_config(N, nb)}
 
     legs = [("bf16", 1), ("fp32", 1), ("bf16", 512), ("fp32", 512)]
     if args.only:
@@ -512,7 +515,7 @@ def main():
         flops = flops_per_frame * K1                      # one launch = one clip
         ach = flops / (r["per_launch_ms"] * 1e-3) / 1e12
         line["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                            "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic_bytes("bf16_hop1"),
+                            "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic_bytes("bf16_hop1", r["config"]),
                             "kernel": "k_mfma_win<bf16> (configuration %d), hop 1, one 160000-sample clip x 128 "
                                       "scales per launch" % r["config"],
                             "alg_flop_per_launch": flops, "avg_launch_ms": r["per_launch_ms"]}
@@ -522,7 +525,7 @@ def main():
         gbs = byt / (r["per_launch_ms_direct"] * 1e-3) / 1e9
         line["roofline_hop512"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                    "frac": gbs / PEAK_HBM_GBS, "alg_bytes_per_launch": byt,
-                                   "traffic": traffic_bytes("bf16_hop512"), "avg_launch_ms": r["per_launch_ms_direct"],
+                                   "traffic": traffic_bytes("bf16_hop512", r["config"]), "avg_launch_ms": r["per_launch_ms_direct"],
                                    "kernel": "k_mfma_persistent_win<bf16> (configuration %d), hop 512, %d clips "
                                              "per launch" % (r["config"], nb)}
 

@@ -153,11 +153,18 @@ cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out);
 
 /* Kernel configuration of the plan (index into the candidate list) and the
  * number of candidates; a forced choice via cwt_plan_set_config.  A plan left
- * at its default configuration (neither set nor tuned) may run a launch with
- * few frames under a smaller-tile candidate instead (BF16, FP16 and BF16x3
- * results do not depend on the configuration); a set or tuned configuration
- * is used for every launch. */
+ * at its default configuration (neither set nor tuned) may run a launch under
+ * a smaller-tile candidate instead: when the launch has few frames, or when a
+ * larger tile's signal window does not fit LDS (BF16, FP16 and BF16x3 results
+ * do not depend on the configuration); a set or tuned configuration is used
+ * for every launch. */
 int32_t cwt_plan_config(cwt_plan_t plan);
+
+/* The configuration that a launch of n_clips clips of len samples each under
+ * this plan runs (cwt_execute for one clip, a batch of the plan for more):
+ * cwt_plan_config for a set or tuned plan, else the per-launch choice.  Host
+ * only, no device work.  Returns -1 for a NULL plan, len < 1 or n_clips < 1. */
+int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips);
 int32_t cwt_plan_num_configs(cwt_plan_t plan);
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
 

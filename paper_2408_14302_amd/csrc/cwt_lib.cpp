@@ -480,20 +480,24 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
 // Default tile configuration, from configuration sweeps on MI355X (batches of
 // 10 s clips with 128 linear scales, 8 x 60 s at 48 kHz with 256 geometric
 // scales up to 1024, 10 s clips with 64 geometric scales up to 256, hops 1 to
-// 512): two 32-frame blocks per wave in 128-frame tiles (configuration 6) up
-// to hop 128, where tap fragments reused over two frame blocks pay for the
-// longer window; one block per wave in 32-frame tiles (5) beyond, where the
-// window grows with the hop and staging it dominates.  Configuration 6 falls
-// back to 5 when only the latter stages its whole window in LDS.
+// 1024).  6 selects the per-launch choice (set_auto/auto_cfg below): 128-frame
+// tiles with two 32-frame blocks per wave where their window fits and the
+// launch has the work-groups, then 64-frame tiles (4), then 32-frame tiles
+// (5).  Up to hop 128 that is the default whenever configuration 6 stages its
+// whole window in LDS (else 5).  Beyond hop 128 it is the default whenever any
+// of the three does: 256-clip batches ran 11-27% faster at hops 192, 256 and
+// 512 than with 32-frame tiles throughout (tap fragments shared by two frame
+// blocks), equal at 1024 and 4% slower at 384; single clips there have too
+// few frames for the wider tiles and keep 5.  With no whole window, 5.
 static int default_cfg(const cwt_plan_s* p, int hop) {
     if (p->dt == DT_FP32) return 0;
     if (p->dt == DT_FP8) return kFp8Cfg;
-    if (hop > 128) return 5;
-    const MfmaCfg& c6 = kMfmaCfgs[6];
-    const MfmaCfg& c5 = kMfmaCfgs[5];
-    if (clip_layout(p->dt, *p->bank, hop, c6, c6.chunk).s.mode != STAGE_WIN &&
-        clip_layout(p->dt, *p->bank, hop, c5, c5.chunk).s.mode == STAGE_WIN)
-        return 5;
+    auto win = [&](int cfg) {
+        const MfmaCfg& c = kMfmaCfgs[cfg];
+        return clip_layout(p->dt, *p->bank, hop, c, c.chunk).s.mode == STAGE_WIN;
+    };
+    if (hop > 128) return (win(6) || win(4) || win(5)) ? 6 : 5;
+    if (!win(6) && win(5)) return 5;
     return 6;
 }
 
@@ -1204,6 +1208,13 @@ cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs, co
 }
 
 int32_t cwt_plan_config(cwt_plan_t plan) { return plan ? plan->cfg : -1; }
+
+int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips) {
+    if (!plan || len < 1 || n_clips < 1) return -1;
+    if (plan->dt == DT_FP32) return plan->cfg;
+    const int64_t K = (len + plan->hop - 1) / plan->hop;
+    return auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups * n_clips; });
+}
 int32_t cwt_plan_num_configs(cwt_plan_t plan) {
     if (!plan) return -1;
     return plan->dt == DT_FP32 ? 1 : kNumMfmaCfgs;

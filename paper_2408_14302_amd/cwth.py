@@ -40,6 +40,7 @@ _SIGS = {
     "cwt_autotune": (_i32, [_c_plan, _i64, ctypes.POINTER(_i32)]),
     "cwt_plan_config": (_i32, [_c_plan]),
     "cwt_plan_num_configs": (_i32, [_c_plan]),
+    "cwt_plan_launch_config": (_i32, [_c_plan, _i64, _i32]),
     "cwt_plan_set_config": (_i32, [_c_plan, _i32]),
     "cwt_plan_bank_taps": (_i32, [_c_plan, _i32, _vp, _i64]),
     "cwt_image_workspace_bytes": (_i64, []),
@@ -168,6 +169,10 @@ class Plan:
     @property
     def config(self) -> int:
         return int(_lib.cwt_plan_config(self._h))
+
+    def launch_config(self, n: int, clips: int = 1) -> int:
+        """The configuration a launch of `clips` clips of n samples runs."""
+        return int(_lib.cwt_plan_launch_config(self._h, int(n), int(clips)))
 
     @property
     def num_configs(self) -> int:

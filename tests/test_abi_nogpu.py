@@ -78,6 +78,7 @@ def test_no_device_paths_return_codes(lib):
     assert raw.cwt_execute(None, None, 10, None, None) == lib.INVALID_ARG
     assert raw.cwt_num_frames(None, 10) == -1
     assert raw.cwt_plan_num_scales(None) == -1
+    assert raw.cwt_plan_launch_config(None, 100, 1) == -1
     assert raw.cwt_plan_destroy(None) == lib.OK
     assert raw.cwt_batch_destroy(None) == lib.OK
     assert raw.cwt_execute_batch(None, None, None, None, 0, None) == lib.OK

@@ -455,6 +455,28 @@ def test_invalid_arguments(torch, cw):
     assert lib.cwt_plan_destroy(None) == cw.OK
 
 
+def test_launch_configuration_follows_the_launch(torch, cw):
+    """A default plan picks the tile per launch: 128-frame tiles at hop 1,
+    64-frame tiles for a 256-clip batch at hop 512 (the 128-frame window does
+    not fit LDS), 32-frame tiles for one clip there (too few frames); a set
+    configuration holds for every launch, and the results agree bit for bit."""
+    scales = np.arange(1, 129)
+    assert cw.Plan(16000.0, scales, 1, "bf16").launch_config(160000) == 6
+    p = cw.Plan(16000.0, scales, 512, "bf16", signed=True)
+    assert p.config == 6
+    assert p.launch_config(160000, 256) == 4 and p.launch_config(160000, 1) == 5
+    assert p.launch_config(0, 1) == -1 and p.launch_config(100, 0) == -1
+    xs = [torch.from_numpy(clip(2, i % 3, 160000, 0.0)).cuda() for i in range(256)]
+    auto = cw.execute_batch([p] * 256, xs)
+    p.set_config(5)
+    assert p.launch_config(160000, 256) == 5
+    fixed = cw.execute_batch([p] * 256, xs)
+    torch.cuda.synchronize()
+    for i in (0, 1, 2, 255):
+        assert torch.equal(auto[i], fixed[i]), i
+    assert cw.Plan(16000.0, scales, 512, "fp8").launch_config(160000, 256) == 5
+
+
 def test_frequencies_and_autotune(torch, cw):
     p = cw.Plan(16000.0, [1.0, 5.0, 100.0], 32, "bf16")
     hz = p.frequencies()
