@@ -44,11 +44,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "config": 6, "fetch_kib": 1804.20, "write_kib": 80000.05,
-                  "src_sha256": "565088f8726c3831b4a1a8b2dd1ed08c22e95648ca5a5d6a092c4f2fd1331bf8"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 86171.09,
-                    "write_kib": 55145.79,
-                    "src_sha256": "565088f8726c3831b4a1a8b2dd1ed08c22e95648ca5a5d6a092c4f2fd1331bf8"},
+    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "config": 6, "fetch_kib": 1804.25, "write_kib": 80000.00,
+                  "src_sha256": "b0d670defaa98a4c6054fc9f3a2315455a6147f43daf4628a04f96e494e13af3"},
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 86177.38,
+                    "write_kib": 55154.17,
+                    "src_sha256": "b0d670defaa98a4c6054fc9f3a2315455a6147f43daf4628a04f96e494e13af3"},
 }
 
 

@@ -168,12 +168,23 @@ static Staging linear_staging(int dt, int hop, int F, int chunk) {
     const int64_t cs = len_u + s.cso;
     s.bytes = (int64_t)s.copies * cs * 16 * P;
     s.raw_bytes = (((len_u + 1) * U + 255) & ~int64_t(255)) * 4;   // raw_floats() in mfma.hip
+    // One copy and an even frame stride q (16-byte units): lane n of a read
+    // hits unit n*q + c, so the 8 lanes of a b128 pass share only 16 / 2^v of
+    // the 16 unit slots of 256 bytes (2^v the largest power of two dividing
+    // q): 4-way conflicts from v = 3 on, 8-way from v = 4.  XOR of the unit's
+    // low four bits with the four bits above bit v spreads them over distinct
+    // slots for every even q (a bijection within each aligned block of 16
+    // units; checked for all offsets c and q up to 256 in a model of the
+    // reads).  Applied from v = 3 on and for powers of two; where the
+    // conflicts are at most 2-way (hops 48 and 96) its address arithmetic cost
+    // more than it saved (single 10 s clips 9.2 -> 11.1 and 10.2 -> 12.0 us),
+    // while at hops 192-768 256-clip batches ran 1.35-2x faster with it.
     s.swz = -1;
     const int64_t q = hop / U;
-    if (s.copies == 1 && hop % U == 0 && q % 2 == 0 && (hop & (hop - 1)) == 0) {
-        int sh = 0;
-        while ((int64_t(1) << sh) < q) ++sh;
-        s.swz = sh;                            // XOR swizzle for power-of-two hops
+    if (s.copies == 1 && hop % U == 0 && q % 2 == 0) {
+        int v = 0;
+        while (((q >> v) & 1) == 0) ++v;
+        if (v >= 3 || (q & (q - 1)) == 0) s.swz = v;
     }
     return s;
 }

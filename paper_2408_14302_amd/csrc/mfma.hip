@@ -14,9 +14,10 @@
 //           its scale blocks, converted once from global memory and shared by
 //           up to four blocks (one per wave); kept in `copies` copies shifted
 //           by multiples of gcd(hop, U) so every lane's 16-byte read is aligned
-//           (U = elements per 16 bytes); for power-of-two hops an XOR swizzle
-//           of the 16-byte unit index spreads the frame-strided reads over the
-//           LDS banks.  The default whenever the window fits.
+//           (U = elements per 16 bytes); with one copy and an even frame
+//           stride an XOR swizzle of the 16-byte unit index spreads the
+//           frame-strided reads over the LDS banks.  The default whenever the
+//           window fits.
 //   LINEAR  the same layout, walked in chunks of `chunk_steps` K-steps through
 //           two LDS buffers fed from a raw FP32 window (very wide scales at
 //           small hops).

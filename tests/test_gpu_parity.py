@@ -187,6 +187,9 @@ EDGE = [
     ("hop 16", 9000, [1.0, 64.0, 33.3], 16),
     ("hop 24", 9000, [1.0, 64.0, 33.3], 24),
     ("hop 48 (rows staging)", 9000, [1.0, 64.0, 33.3], 48),
+    ("hop 96 (even stride, unswizzled)", 20000, [1.0, 64.0, 33.3], 96),
+    ("hop 192 (swizzled stride)", 40000, [1.0, 64.0, 33.3], 192),
+    ("hop 384 (swizzled stride, 2 blocks)", 80000, list(range(1, 41)), 384),
     ("hop 1000", 40000, [1.0, 64.0, 128.0], 1000),
     ("duplicates, unsorted", 4000, [9.0, 1.0, 9.0, 0.05, 3.0], 5),
     ("tile tail", 128 * 3 + 5, list(range(1, 9)), 1),
@@ -287,7 +290,7 @@ def test_impulse_response_on_device(torch, cw, dt):
 def test_bitwise_repeatable_and_config_independent(torch, cw, dt):
     x = clip(2, 1, 160000, 0.0)
     xd = torch.from_numpy(x).cuda()
-    for hop in (1, 3, 256):
+    for hop in (1, 3, 256, 384):
         p = cw.Plan(16000.0, np.arange(1, 129), hop, dt, signed=True)
         a = p(xd)
         b = p(xd)
