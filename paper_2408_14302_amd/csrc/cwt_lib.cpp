@@ -138,6 +138,10 @@ struct Staging {
 static const int64_t kLdsBudget = 52 * 1024;   // chunked tiles: three work-groups per CU
 static const int64_t kWinBudget = 80 * 1024;   // WIN tiles: at least two work-groups per CU
 
+// LDS after a WIN tile's window: its group's output rows (up to four blocks of
+// kBlockRows int32) and, for FP8, their descale factors (float).
+static int64_t win_row_bytes(int dt) { return (dt == DT_FP8 ? 2 : 1) * 4 * kBlockRows * 4; }
+
 // Extra 16-byte units between the shifted copies of a linear window, by hop
 // mod 128 (copies > 1 only).  The X-fragment reads of a wave hit lane
 // addresses (p % U / gh) * stride + p / U, p = frame * hop + 8 * half; this
@@ -536,6 +540,7 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
         const int ws = std::min(c.ws, wb);
         const int F = 32 * c.A * (4 / ws);
         Staging s = linear_staging(dt, hop, F, bk.win_steps[log2_small(wb)]);
+        s.bytes += win_row_bytes(dt);
         if (s.bytes <= kWinBudget) {
             s.mode = STAGE_WIN;
             s.raw_bytes = 0;

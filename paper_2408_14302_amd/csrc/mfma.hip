@@ -709,6 +709,19 @@ __device__ __forceinline__ void load_rows(const MfmaBlock* __restrict__ B, int h
     }
 }
 
+// The same from the copy of a group's rows that WIN tiles keep in LDS beside
+// their window (slot: the block's place in its group).  LDS reads wait on
+// their own counter, not behind the wave's outstanding stores.
+template <int DT>
+__device__ __forceinline__ void lds_rows(const int* srow, const float* sscale, int slot, int hg, RowMap<DT>& m) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rr = kBlockRows * slot + 8 * (v >> 2) + 4 * hg + (v & 3);
+        m.row[v] = srow[rr];
+        if constexpr (DT == DT_FP8) m.scale[v] = sscale[rr];
+    }
+}
+
 // Epilogue of one 32x32 accumulator: FP8 descale, |.| unless signed output,
 // non-temporal stores of the lane's column k.
 template <int DT>
@@ -916,12 +929,14 @@ __device__ __forceinline__ int wave_block(int i, int ws, int WS, int WB, int til
     return (i & 1) ? 2 * WS * r + 2 * WS - 1 - ws : 2 * WS * r + ws;
 }
 
-// K-steps, MFMAs and epilogue of one block for the wave's A frame blocks
-// (fb0 ..); ta/tb hold the block's first eight tap fragments on entry.
-template <int DT, int A, bool EARLY>
+// K-steps, MFMAs and epilogue of one block (slot `slot` of its group) for
+// the wave's A frame blocks (fb0 ..); ta/tb hold the block's first eight tap
+// fragments on entry.
+template <int DT, int A>
 __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, const Geo& g, const uint8_t* lds,
-                                          const MfmaBlock* __restrict__ B, int glo, int64_t k0, int fb0,
-                                          float inv_beta, Frag<DT> (&ta)[4], Frag<DT> (&tb)[4]) {
+                                          const int* srow, const float* sscale, const MfmaBlock* __restrict__ B,
+                                          int slot, int glo, int64_t k0, int fb0, float inv_beta,
+                                          Frag<DT> (&ta)[4], Frag<DT> (&tb)[4]) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 31, hg = lane >> 5;
     const int lo = B->lo, elo = B->elo, ns = (B->ehi - elo + 4) & ~3;   // steps, rounded up to four
@@ -931,8 +946,6 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
     for (int fa = 0; fa < A; ++fa)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[fa][v] = 0.0f;
-    RowMap<DT> rm;
-    if constexpr (EARLY) load_rows<DT>(B, hg, rm);    // in flight during the K loop
     int base[A], unit0[A];
     if (g.swz >= 0) {
         lane_bases<DT, A, LM_LINEAR_SWZ>(c, g, fb0, base, unit0);
@@ -943,7 +956,8 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
         compute_chunk<DT, A, LM_LINEAR, true>(lds, g, 31, base, unit0, glo, elo - glo, ns, elo + ns - 1, lo, tbase,
                                               ta, tb, acc);
     }
-    if constexpr (!EARLY) load_rows<DT>(B, hg, rm);   // where registers are short
+    RowMap<DT> rm;
+    lds_rows<DT>(srow, sscale, slot, hg, rm);
 #pragma unroll
     for (int fa = 0; fa < A; ++fa) {
         const int64_t k = k0 + 32 * (fb0 + fa) + n;
@@ -957,7 +971,7 @@ __device__ __forceinline__ void win_block(const MfmaArgs& a, const ClipArg& c, c
 // group w / WS (A frame blocks) and runs its share of the group's blocks
 // (wave_block) one after the other: the stores of one block drain while the
 // next one's MFMAs run.
-template <int DT, int A, bool EARLY>
+template <int DT, int A>
 __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
                                                  uint8_t* lds, float* red) {
     using T = Tr<DT>;
@@ -993,10 +1007,19 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
     };
     if (j < nb) prefetch(a.blocks + b0 + j);
     win_stage<DT, WinOcc<DT, A>::SF>(c, g, k0 * c.hop + (int64_t)T::KS * glo, al16, beta, lds);
+    // the group's output rows (and FP8 descale factors) beside the window,
+    // in the room the host reserves after it (kWinRowBytes)
+    int* srow = (int*)(lds + T::PLANES * g.plane_bytes);
+    float* sscale = (float*)(srow + 4 * kBlockRows);
+    for (int i = threadIdx.x; i < nb * kBlockRows; i += kMfmaWaves * kWaveSize) {
+        const MfmaBlock* __restrict__ Bi = a.blocks + b0 + i / kBlockRows;
+        srow[i] = Bi->rows[i % kBlockRows];
+        if constexpr (DT == DT_FP8) sscale[i] = Bi->inv_alpha[i % kBlockRows];
+    }
     lds_barrier();
     for (int i = 0; j < nb; j = wave_block(++i, ws, WS, WB, tile)) {
         if (i > 0) prefetch(a.blocks + b0 + j);
-        win_block<DT, A, EARLY>(a, c, g, lds, a.blocks + b0 + j, glo, k0, A * wf, inv_beta, ta, tb);
+        win_block<DT, A>(a, c, g, lds, srow, sscale, a.blocks + b0 + j, j, glo, k0, A * wf, inv_beta, ta, tb);
     }
 }
 
@@ -1038,8 +1061,7 @@ void k_mfma_win(MfmaArgs a) {
     if (a.xcd_remap) id = xcd_remap(id, gridDim.x);
     const int ng = (a.ngroups + a.clip.wb - 1) / a.clip.wb;
     const int tile = id / ng, grp = id - tile * ng;
-    // the row map rides through the K loop only where the register budget has room
-    process_tile_win<DT, A, A == 2 && !WinOcc<DT, A>::wide>(a, a.clip, tile, grp, lds, red);
+    process_tile_win<DT, A>(a, a.clip, tile, grp, lds, red);
 }
 
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
@@ -1086,7 +1108,7 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
         {
             const int ng = (a.ngroups + c.wb - 1) / c.wb;
             const int tile = local / ng, grp = local - tile * ng;
-            process_tile_win<DT, A, false>(a, c, tile, grp, lds, red);
+            process_tile_win<DT, A>(a, c, tile, grp, lds, red);
         }
         lds_barrier();                          // LDS free for the next tile
     }
