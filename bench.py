@@ -44,11 +44,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "config": 6, "fetch_kib": 1802.19, "write_kib": 80000.33,
-                  "src_sha256": "1b21ea08adca52d427c2c642ed73c46b318d722b7c0ee01c329d2f47ecc229b9"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87339.82,
-                    "write_kib": 56089.99,
-                    "src_sha256": "1b21ea08adca52d427c2c642ed73c46b318d722b7c0ee01c329d2f47ecc229b9"},
+    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "config": 6, "fetch_kib": 1802.22, "write_kib": 80000.01,
+                  "src_sha256": "b24e8253cc5a64d52d1149893497f10fb6b62c5e0b5514b437e47a47cac2829d"},
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87360.46,
+                    "write_kib": 56086.55,
+                    "src_sha256": "b24e8253cc5a64d52d1149893497f10fb6b62c5e0b5514b437e47a47cac2829d"},
 }
 
 

@@ -55,7 +55,9 @@ typedef enum {
     CWT_DTYPE_FP16 = 2,    /* FP16 operands on MFMA, FP32 accumulation                */
     CWT_DTYPE_BF16X3 = 3,  /* hi+lo BF16 split, three MFMA products, FP32 accumulation */
     CWT_DTYPE_FP8_E4M3 = 4 /* OCP e4m3 operands on MFMA; power-of-two scale per scale
-                              (taps) and per tile (signal), removed in the epilogue    */
+                              (taps) and per 128-frame segment up to hop 128, per
+                              tile beyond (signal), removed in the epilogue; results
+                              independent of configuration and batch                   */
 } cwt_dtype;
 
 typedef enum { CWT_OUT_MAGNITUDE = 0, CWT_OUT_SIGNED = 1 } cwt_output;

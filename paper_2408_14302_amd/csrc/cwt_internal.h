@@ -15,6 +15,8 @@ enum Dtype : int { DT_FP32 = 0, DT_BF16 = 1, DT_FP16 = 2, DT_BF16X3 = 3, DT_FP8 
 constexpr int kBlockRows = 32;     // scales per MFMA block (the M side of 32x32xK)
 constexpr int kWaveSize = 64;
 constexpr int kMfmaWaves = 4;      // waves per MFMA work-group (split along frames)
+constexpr int kFp8Segment = 128;        // frames per FP8 signal-scale segment (the largest FP8 tile)
+constexpr int kFp8SegmentMaxHop = 128;  // FP8 scales per segment up to this hop, per tile beyond
 constexpr int kDirectFrames = 64;  // frames per direct-sum work-group (one per lane)
 constexpr int kDirectRows = 16;    // scales per direct-sum wave
 constexpr int kDirectWaves = 4;    // waves per direct-sum work-group

@@ -114,7 +114,7 @@ static const MfmaCfg kMfmaCfgs[] = {
     {8, 4, 1, 32},   // 12: 1024 frames, every wave runs all 4 blocks (WIN only, BF16/FP16)
 };
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
-static const int kFp8Cfg = 5;   // the one FP8 configuration (see cfg_fits)
+static const int kFp8Cfg = 5;   // FP8's fallback configuration (see cfg_fits)
 
 static int elem_bytes(int dt) { return dt == DT_FP8 ? 1 : 2; }
 static int planes_of(int dt) { return dt == DT_BF16X3 ? 2 : 1; }
@@ -506,11 +506,14 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
 // few frames for the wider tiles and keep 5.  With no whole window, 5.
 static int default_cfg(const cwt_plan_s* p, int hop) {
     if (p->dt == DT_FP32) return 0;
-    if (p->dt == DT_FP8) return kFp8Cfg;
     auto win = [&](int cfg) {
         const MfmaCfg& c = kMfmaCfgs[cfg];
         return clip_layout(p->dt, *p->bank, hop, c, c.chunk).s.mode == STAGE_WIN;
     };
+    // FP8 takes the per-launch choice only where its last resort, 5, stages
+    // the whole window too: no FP8 launch may fall back to a chunked tile of
+    // 256 frames (see cfg_fits)
+    if (p->dt == DT_FP8) return hop <= kFp8SegmentMaxHop && win(5) && (win(6) || win(4)) ? 6 : kFp8Cfg;
     if (hop > 128) return (win(6) || win(4) || win(5)) ? 6 : 5;
     if (!win(6) && win(5)) return 5;
     return 6;
@@ -519,10 +522,17 @@ static int default_cfg(const cwt_plan_s* p, int hop) {
 static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     if (p->dt == DT_FP32) return cfg == 0;
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
-    // FP8 scales the signal per tile; one fixed tile geometry keeps every
-    // clip's result independent of the configuration and of its batch.
-    if (p->dt == DT_FP8) return cfg == kFp8Cfg;
     const MfmaCfg& c = kMfmaCfgs[cfg];
+    // FP8 scales the signal per 128-frame segment up to hop 128 (fp8_beta):
+    // every tile must lie in one segment, i.e. have at most 128 frames.
+    // Configuration 5 (32-frame WIN, 128-frame chunked and 32-128-frame row
+    // tiles) always does; 4 and 6 (two frame blocks per wave) only with WIN
+    // tiles of 64 and 128 frames, their chunked tiles having 256.  Beyond hop
+    // 128 the scale is per tile and 5 is the only configuration.
+    if (p->dt == DT_FP8)
+        return cfg == kFp8Cfg ||
+               (hop <= kFp8SegmentMaxHop && (cfg == 4 || cfg == 6) &&
+                clip_layout(p->dt, *p->bank, hop, c, c.chunk).s.mode == STAGE_WIN);
     if (c.A == 8)   // WIN tiles of the 2-byte types only
         return (p->dt == DT_BF16 || p->dt == DT_FP16) &&
                clip_layout(p->dt, *p->bank, hop, c, c.chunk).s.mode == STAGE_WIN;
@@ -813,7 +823,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     // LDS (operand buffers plus raw window) fits the budget.  WIN and SPLIT
     // clips have a fixed geometry per (bank, hop, configuration).
     const bool fp32 = p0->dt == DT_FP32;
-    const int cfg = auto_cfg(p0, [&](const ClipLayout& L) {
+    int cfg = auto_cfg(p0, [&](const ClipLayout& L) {
         int64_t t = 0;
         for (int i = 0; i < n; ++i) {
             const int64_t K = (lens[i] + plans[i]->hop - 1) / plans[i]->hop;
@@ -825,13 +835,29 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     bool cached_ok = true;   // plans[i]->lay is valid for this launch when plans[i]->cfg == cfg
     int chunk = 8;
     bool any_linear = false, all_win = true;
-    for (int i = 0; i < n && !fp32; ++i)
-        if (lens[i] > 0) {
-            const ClipLayout& L = plans[i]->cfg == cfg ? plans[i]->lay
-                                  : clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk);
-            any_linear = any_linear || L.s.mode == STAGE_LINEAR;
-            all_win = all_win && L.s.mode == STAGE_WIN;
-        }
+    auto scan = [&]() {
+        any_linear = false;
+        all_win = true;
+        for (int i = 0; i < n && !fp32; ++i)
+            if (lens[i] > 0) {
+                const ClipLayout& L = plans[i]->cfg == cfg ? plans[i]->lay
+                                      : clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk);
+                any_linear = any_linear || L.s.mode == STAGE_LINEAR;
+                all_win = all_win && L.s.mode == STAGE_WIN;
+            }
+    };
+    scan();
+    bool fp8_large_hop = false;
+    for (int i = 0; i < n; ++i) fp8_large_hop = fp8_large_hop || plans[i]->hop > kFp8SegmentMaxHop;
+    if (p0->dt == DT_FP8 && cfg != kFp8Cfg && (!all_win || fp8_large_hop)) {
+        // every FP8 tile must lie in one 128-frame segment, and clips beyond
+        // hop 128 (a scale per tile) have only configuration 5: a clip that
+        // this configuration gives chunked (256-frame) tiles, or one beyond
+        // hop 128, sends the batch to 5
+        cfg = kFp8Cfg;
+        c = kMfmaCfgs[cfg];
+        scan();
+    }
     if (c.A == 8 && !all_win) {
         // 256-frame waves exist for WIN tiles only: run this batch with A = 4
         c.A = 4;
@@ -1100,7 +1126,8 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
             }
         }
         if (!tuned && p->cfg == 6) set_auto(p.get());
-        if (!cfg_fits(p.get(), p->cfg, hop)) {
+        // an automatic plan's 6 stands for the per-launch choice (auto_cfg)
+        if (!p->cfg_auto && !cfg_fits(p.get(), p->cfg, hop)) {
             bool found = false;
             for (int c = 0; c < (p->dt == DT_FP32 ? 1 : kNumMfmaCfgs); ++c)
                 if (cfg_fits(p.get(), c, hop)) {

@@ -451,9 +451,9 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // Power-of-two signal scale beta = 2^floor(log2(448 / max|x~|)), the maximum
-// taken over exactly the samples the tile's frames touch (the union of the
-// windows [(k0+f)*hop + KS*glo, (k0+f)*hop + KS*(ghi+1)) ), so beta depends only
-// on the tile's frame range and the scale group, never on the staging layout.
+// taken over the samples that frames k0 .. k0+F-1 touch in the K range
+// [glo, ghi] (the union of the windows [(k0+f)*hop + KS*glo,
+// (k0+f)*hop + KS*(ghi+1)) ).
 template <int DT>
 __device__ float tile_beta(const ClipArg& c, int F, int64_t k0, int glo, int ghi, float* red) {
     using T = Tr<DT>;
@@ -484,6 +484,21 @@ __device__ float tile_beta(const ClipArg& c, int F, int64_t k0, int glo, int ghi
     int e;
     frexp(448.0 / (double)m, &e);     // 448/m = f * 2^e, f in [0.5, 1)
     return (float)ldexp(1.0, e - 1);
+}
+
+// The FP8 tile scale.  Up to hop kFp8SegmentMaxHop: beta of the
+// kFp8Segment-frame segment that holds the tile, over the K range of the
+// bank's widest block (the last: blocks are sorted by scale); every FP8 tile
+// there has 32, 64 or 128 frames and starts at a multiple of its size, so it
+// lies in one segment, and beta, hence every FP8 result, is the same for
+// every tile configuration and batch.  Beyond, where a segment's samples
+// outnumber a 32-frame tile's several times over, beta of the tile's own
+// frames and K range (glo, ghi), FP8 then having one configuration.
+template <int DT>
+__device__ float fp8_beta(const MfmaArgs& a, const ClipArg& c, int F, int64_t k0, int glo, int ghi, float* red) {
+    if (c.hop > kFp8SegmentMaxHop) return tile_beta<DT>(c, F, k0, glo, ghi, red);
+    const MfmaBlock* __restrict__ W = a.blocks + a.ngroups - 1;
+    return tile_beta<DT>(c, kFp8Segment, k0 / kFp8Segment * kFp8Segment, W->lo, W->hi, red);
 }
 
 template <int DT>
@@ -761,7 +776,7 @@ __device__ __forceinline__ void process_tile_split(const MfmaArgs& a, const Clip
     const Geo g = make_geo<DT>(c, F, chunk);
     const bool al16 = (((uintptr_t)c.x) & 15) == 0;
     float beta = 1.0f;
-    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
+    if constexpr (DT == DT_FP8) beta = fp8_beta<DT>(a, c, F, k0, glo, ghi, red);
 
     f32x16 acc[1];
 #pragma unroll
@@ -822,7 +837,7 @@ __device__ __forceinline__ void process_tile(const MfmaArgs& a, const ClipArg& c
     const Geo g = make_geo<DT>(c, F, a.chunk_steps);
     const bool al16 = (((uintptr_t)c.x) & 15) == 0;
     float beta = 1.0f;
-    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, lo, hi, red);
+    if constexpr (DT == DT_FP8) beta = fp8_beta<DT>(a, c, F, k0, lo, hi, red);
 
     f32x16 acc[A];
 #pragma unroll
@@ -988,7 +1003,7 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
     const Geo g = make_geo<DT>(c, F, ghi - glo + 1);
     const bool al16 = (((uintptr_t)c.x) & 15) == 0;
     float beta = 1.0f;
-    if constexpr (DT == DT_FP8) beta = tile_beta<DT>(c, F, k0, glo, ghi, red);
+    if constexpr (DT == DT_FP8) beta = fp8_beta<DT>(a, c, F, k0, glo, ghi, red);
     const float inv_beta = 1.0f / beta;
 
     // taps of the first steps of the wave's first block (compute_chunk with

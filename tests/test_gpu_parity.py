@@ -286,7 +286,7 @@ def test_impulse_response_on_device(torch, cw, dt):
 # Determinism: the summation order is fixed, so results are bit-identical
 # run to run and across kernel configurations.
 
-@pytest.mark.parametrize("dt", ["bf16", "fp16", "bf16x3", "fp32"])
+@pytest.mark.parametrize("dt", ["bf16", "fp16", "bf16x3", "fp8", "fp32"])
 def test_bitwise_repeatable_and_config_independent(torch, cw, dt):
     x = clip(2, 1, 160000, 0.0)
     xd = torch.from_numpy(x).cuda()
@@ -477,7 +477,11 @@ def test_launch_configuration_follows_the_launch(torch, cw):
     torch.cuda.synchronize()
     for i in (0, 1, 2, 255):
         assert torch.equal(auto[i], fixed[i]), i
-    assert cw.Plan(16000.0, scales, 512, "fp8").launch_config(160000, 256) == 5
+    # FP8: the per-launch choice up to hop 128 (a signal scale per 128-frame
+    # segment), 32-frame tiles beyond (a scale per tile)
+    assert cw.Plan(16000.0, scales, 1, "fp8").launch_config(160000, 3) == 6
+    p8 = cw.Plan(16000.0, scales, 512, "fp8")
+    assert p8.launch_config(160000, 256) == 5 and p8.launch_config(160000, 1) == 5
 
 
 def test_frequencies_and_autotune(torch, cw):
