@@ -537,7 +537,7 @@ def main():
         sclips = [torch.from_numpy(synth.make_clip(1430500 + i, int(n), FS, 0.0)).to(dev) for i, n in enumerate(lens)]
         plans = {(s_, h): cwth.Plan(FS, synth.linear_scales(s_), h, "bf16") for s_ in (64, 128) for h in (1, 256, 512)}
         ex = serve.GpuExecutor(3, max_clips=64)
-        # warm every plan and captured-graph shape once, untimed
+        # warm every plan and batch shape once, untimed
         serve.serve_session(400.0, 1.0, sclips, plans, seed=7, executor=ex)
         stats, reqs = serve.serve_session(args.qps, args.serve_seconds, sclips, plans, seed=1430401, executor=ex)
         sm = stats.summary()

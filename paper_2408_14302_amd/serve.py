@@ -180,7 +180,7 @@ class Scheduler:
 class GpuExecutor:
     """Runs each admitted batch as one persistent launch on the slot's stream."""
 
-    def __init__(self, slots: int, max_clips: int = 256, keep_outputs: bool = False):
+    def __init__(self, slots: int, max_clips: int = 256, keep_outputs: bool = False, graph: bool = False):
         import torch
 
         from . import cwth
@@ -189,6 +189,11 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(slots)]   # default priority
         self.batches = [cwth.Batch(max_clips) for _ in range(slots)]
         self.keep = keep_outputs
+        # Direct launches by default: serving batches change from launch to
+        # launch, and a graph replay (kernel-node update plus ~8 us of
+        # device-side launch processing) measured p50 0.33 ms against 0.17 ms
+        # at half saturation, for 2-4% more requests/s at saturation.
+        self.graph = graph
 
     def launch(self, slot: int, batch: List[Request]):
         torch = self.torch
@@ -199,7 +204,7 @@ class GpuExecutor:
             outs = [torch.empty((p.num_scales, p.num_frames(x.numel())), dtype=torch.float32, device=x.device)
                     for p, x in zip(plans, xs)]
             # inputs were produced on another stream: order them before this launch
-            self.batches[slot](plans, xs, outs, stream=st, graph=True)
+            self.batches[slot](plans, xs, outs, stream=st, graph=self.graph)
             ev = torch.cuda.Event()
             ev.record(st)
         for r, o in zip(batch, outs):
@@ -256,8 +261,8 @@ def serve_session(qps: float, duration_s: float, clips, plans, scale_sets=(64, 1
                   budget_bytes: int = 4 << 30, slots: int = 3, max_batch: int = 64, seed: int = 1430400,
                   keep_outputs: bool = False, executor: Optional[GpuExecutor] = None):
     """One Poisson session on the GPU; returns (Stats, requests).  Pass the same
-    executor to several sessions to keep its batch contexts (and their captured
-    graphs) warm."""
+    executor to several sessions to keep its batch contexts (and, in graph
+    mode, their captured graphs) warm."""
     import torch
     count = max(1, int(round(qps * duration_s)))
     reqs = poisson_requests(seed, count, qps, clips, plans, scale_sets, hops)
