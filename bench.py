@@ -161,7 +161,7 @@ def hop_sweep(torch, cwth, synth, dev, scales, args):
             outs = [[torch.empty((S, K), dtype=torch.float32, device=dev) for _ in range(nb)] for _ in range(2)]
             prep = [B.prepare([plan] * nb, sets[j], outs[j]) for j in range(2)]
             steps = max(3, min(args.steps, 20 if dt == "bf16" else 5))
-            total, per = time_launches(torch, lambda s_: prep[s_ % 2].run(stream=stream.cuda_stream, graph=True), 2,
+            total, per = time_launches(torch, lambda s_: prep[s_ % 2].run(stream=stream.cuda_stream, graph=False), 2,
                                        steps, min(args.warmup, 3), warm_ms=30.0)
             ms = float(np.mean(per))
             coeffs = nb * S * K
@@ -283,7 +283,7 @@ def image_bench(torch, cwth, synth, dev, scales, args):
 def long_bench(torch, cwth, synth, dev, args):
     """Long multichannel recordings: 8 channels x 60 s at 48 kHz (2,880,000
     samples each), 256 geometric scales from 1 to 1024 samples, hops 128 and
-    512, all channels in one persistent launch (prepared batch, graph replay,
+    512, all channels in one persistent launch (prepared batch, direct launch,
     two input/output sets in alternation).  Reports coefficients/s, the
     algorithmic TFLOP/s and its fraction of the dtype's dense peak (BF16
     2.5 PFLOP/s, FP8 5.0, FP32 VALU 157.3 TFLOP/s), and FP8 and BF16 over FP32."""
@@ -303,7 +303,7 @@ def long_bench(torch, cwth, synth, dev, args):
             outs = [[torch.empty((256, K), dtype=torch.float32, device=dev) for _ in range(ch)] for _ in range(2)]
             prep = [B.prepare([plan] * ch, sets[j], outs[j]) for j in range(2)]
             steps = max(3, min(args.steps, 20 if dt != "fp32" else 3))
-            _, per = time_launches(torch, lambda s_: prep[s_ % 2].run(stream=stream.cuda_stream, graph=True), 2,
+            _, per = time_launches(torch, lambda s_: prep[s_ % 2].run(stream=stream.cuda_stream, graph=False), 2,
                                    steps, min(args.warmup, 2), warm_ms=30.0)
             ms = float(np.mean(per))
             tflops = flop_per_frame * K * ch / (ms * 1e-3) / 1e12
