@@ -117,8 +117,9 @@ cwt_status cwt_execute(cwt_plan_t plan, const float* x, int64_t len, float* out,
  * float32[n_scales * cwt_num_frames(plans[c], lens[c])]).  All plans must share
  * dtype, output mode and scale set (CWT_ERR_UNSUPPORTED otherwise); hops may
  * differ.  Each clip's result is bit-identical to cwt_execute of that clip.
- * Uses a library-owned batch context for the calling thread and device; see
- * cwt_batch_create for the explicit form.
+ * Uses a library-owned batch context for the calling thread and device and
+ * launches directly (no graph); see cwt_batch_create for the explicit form,
+ * which can also replay the launch as a captured HIP graph.
  */
 cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs,
                              const int64_t* lens, float* const* outs, int32_t n,

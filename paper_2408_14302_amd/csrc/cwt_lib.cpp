@@ -1244,7 +1244,9 @@ cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs, co
             slot = b.release();
         }
         std::lock_guard<std::mutex> lk(slot->mu);
-        return batch_run(slot, plans, xs, lens, outs, n, 1, (hipStream_t)stream);
+        // a direct launch: a graph replay adds ~8 us of device-side launch
+        // processing per call (the explicit context offers it)
+        return batch_run(slot, plans, xs, lens, outs, n, 0, (hipStream_t)stream);
     } catch (...) {
         return fail(CWT_ERR_INTERNAL, "unexpected exception");
     }
