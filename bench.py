@@ -81,7 +81,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["bf16-hop1", "fp32-hop1", "bf16-hop512", "fp32-hop512"], default=None,
+    ap.add_argument("--only", choices=["bf16-hop1", "fp32-hop1", "bf16-hop512", "fp32-hop512", "bf16-hopmixed",
+                                       "fp32-hopmixed"], default=None,
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--hop-sweep", action="store_true",
                     help="cost curve over hops 1, 2, 4, .., 1024 (one JSON line per hop) instead of the metric")
@@ -94,6 +95,8 @@ def parse():
     ap.add_argument("--long", action="store_true",
                     help="8 channels x 60 s at 48 kHz, 256 geometric scales 1..1024, hops 128 and 512, "
                          "BF16 / FP8 / FP32 (JSON lines)")
+    ap.add_argument("--errors", action="store_true",
+                    help="error of every path against the FP64 oracle per workload, dtype and hop (JSON lines)")
     ap.add_argument("--dwt-clips", default="3,256", help="batch sizes for --dwt (comma separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
@@ -373,6 +376,62 @@ def dwt_bench(torch, cwth, synth, dev, scales, args):
         del xs, pyr, out
 
 
+def error_report(torch, cwth, synth, dev, args):
+    """Measured error of every floating-point path against the FP64 oracle,
+    one JSON line per (workload, dtype, hop): rel-L2 and max-abs over the
+    whole signed scalogram, the worst single scale's rel-L2, and the stated
+    tolerance.  Workloads: 1 s / 32 scales (hops 1, 64); 10 s / 128 scales,
+    SNR -6/0/6 dB (hops 1, 32, 128, 256, 512); 8 x 60 s at 48 kHz with 256
+    geometric scales (hops 128, 512; BF16, FP8, BF16x3 and FP32).  Every
+    coefficient is compared (the oracle runs on all host threads)."""
+    import oracle
+    tol = {"fp32": (1e-5, 1e-4), "fp16": (2e-3, 2e-3), "bf16": (1e-2, 1e-2), "bf16x3": (5e-5, 5e-5),
+           "fp8": (1.5e-1, 2e-1)}
+    work = [("1 s at 16 kHz, 32 linear scales, SNR 0 dB", 16000, 16000.0, synth.linear_scales(32),
+             [synth.make_clip(synth.clip_seed(1, 0), 16000, 16000.0, 0.0)], (1, 64), tuple(tol)),
+            ("10 s at 16 kHz, 128 linear scales, SNR -6/0/6 dB", N, FS, synth.linear_scales(128),
+             [synth.make_clip(synth.clip_seed(2, i), N, FS, snr) for i, snr in enumerate((-6.0, 0.0, 6.0))],
+             (1, 32, 128, 256, 512), tuple(tol)),
+            ("8 x 60 s at 48 kHz, 256 geometric scales 1..1024", 2880000, 48000.0, synth.geometric_scales(256, 1024.0),
+             [synth.make_clip(synth.clip_seed(5, c), 2880000, 48000.0, 0.0) for c in range(8)], (128, 512),
+             ("bf16", "fp8", "bf16x3", "fp32"))]
+    for name, n, fs, scales, clips, hops, dts in work:
+        xs = [torch.from_numpy(c).to(dev) for c in clips]
+        for hop in hops:
+            t0 = time.perf_counter()
+            refs = [oracle.cwt(c.astype(np.float64), scales, hop) for c in clips]
+            osec = time.perf_counter() - t0
+            for dt in dts:
+                plan = cwth.Plan(fs, scales, hop, dt, signed=True)
+                outs = cwth.execute_batch([plan] * len(xs), xs) if len(xs) > 1 else [plan(xs[0])]
+                torch.cuda.synchronize()
+                num = den = 0.0
+                mab = 0.0
+                sn = np.zeros(len(scales))
+                sd = np.zeros(len(scales))
+                for o, ref in zip(outs, refs):
+                    d = o.cpu().numpy().astype(np.float64) - ref
+                    num += float(np.sum(d * d))
+                    den += float(np.sum(ref * ref))
+                    mab = max(mab, float(np.abs(d).max()))
+                    sn += np.sum(d * d, axis=1)
+                    sd += np.sum(ref * ref, axis=1)
+                per_scale = np.sqrt(sn / np.maximum(sd, 1e-300))
+                w = int(np.argmax(per_scale))
+                row = {"metric": "error vs FP64 oracle (signed W, every coefficient)", "workload": name, "dtype": dt,
+                       "hop": hop, "clips": len(clips), "coefficients": int(sum(r.size for r in refs)),
+                       "rel_l2": math.sqrt(num / den), "max_abs": mab, "tol_rel_l2": tol[dt][0],
+                       "tol_max_abs": tol[dt][1], "worst_scale": float(scales[w]),
+                       "worst_scale_rel_l2": float(per_scale[w]), "oracle_seconds": osec}
+                if dt == "fp8":
+                    row["per_scale_rel_l2_quantiles"] = [float(q) for q in np.quantile(per_scale, [0.0, 0.5, 0.9, 1.0])]
+                print(json.dumps(row), flush=True)
+                log("%s hop %d %-6s rel-L2 %.3e (tol %.0e) max-abs %.3e (tol %.0e) worst scale %g: %.3e" % (
+                    name[:22], hop, dt, row["rel_l2"], tol[dt][0], mab, tol[dt][1], scales[w], per_scale[w]))
+                del outs, plan
+            del refs
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -413,6 +472,9 @@ def main():
         return
     if args.long:
         long_bench(torch, cwth, synth, dev, args)
+        return
+    if args.errors:
+        error_report(torch, cwth, synth, dev, args)
         return
     fpc = alg_flops_per_coeff(scales)
     flops_per_frame = float(fpc.sum())                  # all scales, one frame
@@ -473,15 +535,50 @@ def main():
                 "per_launch_ms_graph": float(np.mean(per_graph)), "clips_per_launch": nb, "steps": steps,
                 "config": plan.launch_config(N, nb)}
 
-    legs = [("bf16", 1), ("fp32", 1), ("bf16", 512), ("fp32", 512)]
+    def leg_mixed(dt):
+        """The batching workload: 256 clips, lengths uniform in [1 s, 10 s],
+        SNR uniform in [-6, 6] dB, hop per clip from {64, 256, 512}, 128
+        scales, one persistent launch whose tile configuration is tuned on the
+        batch itself (cwt_autotune_batch); timed as direct launches of the
+        prepared batch and as graph replays."""
+        nb = 256
+        lens = synth.batch_lengths(synth.clip_seed(3, 0), nb)
+        rng = np.random.default_rng(synth.clip_seed(3, 1))
+        snr = rng.uniform(-6.0, 6.0, nb)
+        hops = rng.choice([64, 256, 512], nb)
+        plans = {h: cwth.Plan(FS, scales, h, dt) for h in (64, 256, 512)}
+        pl = [plans[int(h)] for h in hops]
+        base = [torch.from_numpy(synth.make_clip(synth.clip_seed(3, 10 + i), int(lens[i]), FS, float(snr[i]))).to(dev)
+                for i in range(nb)]
+        sets = [base, [b.clone() for b in base]]
+        outs = [[torch.empty((S, p.num_frames(int(n))), dtype=torch.float32, device=dev) for p, n in zip(pl, lens)]
+                for _ in range(2)]
+        chosen = cwth.autotune_batch(pl, lens) if dt != "fp32" else 0
+        B = cwth.Batch(nb)
+        prepared = [B.prepare(pl, sets[j], outs[j]) for j in range(2)]
+        sptr = stream.cuda_stream
+        steps = args.steps if dt == "bf16" else max(5, args.steps // 5)
+        total, per = time_launches(torch, lambda s_: prepared[s_ % 2].run(stream=sptr, graph=False), 2, steps,
+                                   args.warmup)
+        _, per_graph = time_launches(torch, lambda s_: prepared[s_ % 2].run(stream=sptr, graph=True), 2, steps,
+                                     args.warmup)
+        ms = total / steps
+        K = np.array([p.num_frames(int(n)) for p, n in zip(pl, lens)], dtype=np.float64)
+        coeffs = float(S * K.sum())
+        return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": float(np.mean(per)),
+                "per_launch_ms_graph": float(np.mean(per_graph)), "clips_per_launch": nb, "steps": steps,
+                "config": chosen, "alg_bytes": float(4.0 * lens.sum() + 4.0 * coeffs),
+                "alg_flop": float(alg_flops_per_coeff(scales).sum() * K.sum()), "samples": int(lens.sum())}
+
+    legs = [("bf16", 1), ("fp32", 1), ("bf16", 512), ("fp32", 512), ("bf16", "mixed"), ("fp32", "mixed")]
     if args.only:
         d, h = args.only.split("-hop")
-        legs = [(d, int(h))]
+        legs = [(d, h if h == "mixed" else int(h))]
     for dt, hop in legs:
-        log("leg %s hop %d ..." % (dt, hop))
-        r = leg_hop1(dt) if hop == 1 else leg_hop512(dt)
+        log("leg %s hop %s ..." % (dt, hop))
+        r = leg_hop1(dt) if hop == 1 else (leg_hop512(dt) if hop == 512 else leg_mixed(dt))
         result[(dt, hop)] = r
-        log("  %s hop %d: %.3f ms/step, %.3e coeffs/s" % (dt, hop, r["ms_per_step"], r["coeffs_per_s"]))
+        log("  %s hop %s: %.3f ms/step, %.3e coeffs/s" % (dt, hop, r["ms_per_step"], r["coeffs_per_s"]))
 
     head = result.get(("bf16", 1)) or next(iter(result.values()))
     line = {
@@ -504,10 +601,10 @@ def main():
     }
     legs_out = {}
     for (dt, hop), r in result.items():
-        legs_out["%s_hop%d" % (dt, hop)] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
-    for hop in (1, 512):
+        legs_out["%s_hop%s" % (dt, hop)] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+    for hop in (1, 512, "mixed"):
         if ("bf16", hop) in result and ("fp32", hop) in result:
-            legs_out["ratio_bf16_over_fp32_hop%d" % hop] = result[("bf16", hop)]["coeffs_per_s"] / result[("fp32", hop)]["coeffs_per_s"]
+            legs_out["ratio_bf16_over_fp32_hop%s" % hop] = result[("bf16", hop)]["coeffs_per_s"] / result[("fp32", hop)]["coeffs_per_s"]
     line["legs"] = legs_out
 
     # ---------------- roofline of the dominant kernel ----------------
@@ -529,6 +626,18 @@ def main():
                                    "traffic": traffic_bytes("bf16_hop512", r["config"]), "avg_launch_ms": r["per_launch_ms"],
                                    "kernel": "k_mfma_persistent_win<bf16> (configuration %d), hop 512, %d clips "
                                              "per launch" % (r["config"], nb)}
+
+    if ("bf16", "mixed") in result:
+        r = result[("bf16", "mixed")]
+        gbs = r["alg_bytes"] / (r["per_launch_ms"] * 1e-3) / 1e9
+        tfl = r["alg_flop"] / (r["per_launch_ms"] * 1e-3) / 1e12
+        line["roofline_mixed"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                  "frac": gbs / PEAK_HBM_GBS, "alg_bytes_per_launch": r["alg_bytes"],
+                                  "mfma_tflops": tfl, "mfma_frac": tfl / PEAK_BF16_TFLOPS,
+                                  "traffic": traffic_bytes("bf16_mixed", r["config"]),
+                                  "avg_launch_ms": r["per_launch_ms"],
+                                  "kernel": "k_mfma_persistent_win<bf16> (configuration %d), 256 clips of 1-10 s, "
+                                            "hops 64/256/512, one launch" % r["config"]}
 
     # ---------------- serving ----------------
     if not args.no_serve and not args.only:

@@ -145,28 +145,48 @@ cwt_status cwt_batch_execute(cwt_batch_t batch, const cwt_plan_t* plans,
                              void* stream);
 
 /*
- * Time the candidate kernel configurations for this plan at signal length len
- * (synchronous; allocates scratch buffers of its own) and keep the fastest for
- * the plan's (dtype, hop, scale-set) class.  Results are written to the JSON
- * cache named by $CWTH_AUTOTUNE_CACHE (if set) keyed by device arch and CU
- * count, and read back by later plan creations.  chosen_out (host, may be NULL)
- * receives the index of the chosen configuration.
+ * Autotuner.  Times, on the launch described, the per-launch automatic
+ * choice and every kernel configuration that fits every clip's hop
+ * (synchronous; allocates its own input, output and descriptor buffers, fills
+ * the input with a seeded noise signal; the cost does not depend on the
+ * values).  Where a configuration beats the automatic choice by more than 3%,
+ * it is recorded for the launch's class: (device arch and CU count, dtype,
+ * scale count, widest half-width, log2 buckets of the smallest and largest
+ * hop, of the clip count and of the mean length).  Later launches of that
+ * class by plans left at their default configuration run it (cwt_execute,
+ * cwt_execute_batch, cwt_batch_execute, cwt_plan_launch_config); a
+ * configuration set with cwt_plan_set_config is never overridden.  Where the
+ * automatic choice wins, a record of the class is removed.  Records live for
+ * the process and, with $CWTH_AUTOTUNE_CACHE naming a file, in that file
+ * (read on first use, rewritten after every tuning).  BF16, FP16 and BF16x3
+ * results do not depend on the configuration; FP8's do not either, under the
+ * configurations it accepts.
+ *   plans, lens  host arrays of n >= 1 plans (one bank and output mode, hops
+ *                may differ, as in cwt_execute_batch) and lengths >= 1
+ *   chosen_out   host, may be NULL: the configuration such launches now run
+ * Errors: CWT_ERR_INVALID_ARG, CWT_ERR_UNSUPPORTED (plans that cannot share a
+ * launch), CWT_ERR_OUT_OF_MEMORY, CWT_ERR_DEVICE.  FP32 plans have one
+ * configuration; the call then only reports it.
  */
+cwt_status cwt_autotune_batch(const cwt_plan_t* plans, const int64_t* lens, int32_t n, int32_t* chosen_out);
+
+/* cwt_autotune_batch of one clip of len samples (the cwt_execute launch). */
 cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out);
 
 /* Kernel configuration of the plan (index into the candidate list) and the
  * number of candidates; a forced choice via cwt_plan_set_config.  A plan left
- * at its default configuration (neither set nor tuned) may run a launch under
- * a smaller-tile candidate instead: when the launch has few frames, or when a
- * larger tile's signal window does not fit LDS (BF16, FP16 and BF16x3 results
- * do not depend on the configuration); a set or tuned configuration is used
- * for every launch. */
+ * at its default configuration may run a launch under another candidate: a
+ * smaller-tile one when the launch has few frames or a larger tile's signal
+ * window does not fit LDS, or the one tuned for the launch's class
+ * (cwt_autotune_batch); BF16, FP16 and BF16x3 results do not depend on the
+ * configuration.  A set configuration is used for every launch. */
 int32_t cwt_plan_config(cwt_plan_t plan);
 
 /* The configuration that a launch of n_clips clips of len samples each under
  * this plan runs (cwt_execute for one clip, a batch of the plan for more):
- * cwt_plan_config for a set or tuned plan, else the per-launch choice.  Host
- * only, no device work.  Returns -1 for a NULL plan, len < 1 or n_clips < 1. */
+ * cwt_plan_config for a set plan, else the tuned configuration of the
+ * launch's class, else the per-launch choice.  Host only, no device work.
+ * Returns -1 for a NULL plan, len < 1 or n_clips < 1. */
 int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips);
 int32_t cwt_plan_num_configs(cwt_plan_t plan);
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);

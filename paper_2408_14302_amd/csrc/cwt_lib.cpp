@@ -431,47 +431,95 @@ struct cwt_plan_s {
     int device = 0;
     int cus = 0;
     std::string arch;
+    uint64_t arch_hash = 0;   // fnv1a(arch): the device part of a tuned launch class
     std::shared_ptr<Bank> bank;
     ClipLayout lay;      // MFMA layout under cfg ...
     int lay_chunk = 8;   // ... for chunked LINEAR tiles of this chunk
+    bool cfg_user = false;    // configuration set by cwt_plan_set_config: no tuned override
     bool cfg_auto = false;    // default configuration: each launch picks 6, 4 or 5 (auto_cfg)
     ClipLayout auto_lay[3];   // layouts under configurations 6, 4 and 5 for that choice
 };
 
-static std::string tune_key(const cwt_plan_s* p, int64_t len) {
-    // (arch, CUs, dtype, hop bucket, scale count, widest half-width bucket, length bucket)
-    auto bucket = [](int64_t v) {
-        int b = 0;
-        while ((int64_t(1) << (b + 1)) <= v) ++b;
-        return b;
-    };
-    std::ostringstream o;
-    o << p->arch << "/" << p->cus << "/dt" << p->dt << "/h" << bucket(p->hop) << "/S"
-      << p->bank->scales.size() << "/M" << bucket(std::max(1, p->bank->Mmax)) << "/N" << bucket(std::max<int64_t>(1, len));
-    return o.str();
+// ---------------------------------------------------------------------------
+// Tuned launch classes.  cwt_autotune_batch times the configurations on the
+// launch it is given and, where one beats the automatic per-launch choice by
+// more than kTuneMargin, records it for the launch's class: (arch, CUs, dtype,
+// scale count, widest half-width bucket, hop buckets of the batch, clip-count
+// bucket, mean-length bucket).  Launches of a plan left at its default
+// configuration look their class up (cwt_execute, batches, launch_config); a
+// configuration set with cwt_plan_set_config is never overridden.  The
+// classes are kept per process and, with $CWTH_AUTOTUNE_CACHE set, in that
+// file ("class": index lines of a JSON object), read on first use.
+static const double kTuneMargin = 0.03;
+
+static int log2_bucket(int64_t v) {
+    int b = 0;
+    while (b < 62 && (int64_t(1) << (b + 1)) <= v) ++b;
+    return b;
+}
+
+// A launch class.  Held as integers, so a launch looks its class up without
+// allocating; written to and read from the cache file as text.
+struct TuneKey {
+    uint64_t arch;   // FNV-1a hash of the device's arch name
+    int cus, dt, S, Mb, hlo, hhi, C, N;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, cus, dt, S, Mb, hlo, hhi, C, N) <
+               std::tie(o.arch, o.cus, o.dt, o.S, o.Mb, o.hlo, o.hhi, o.C, o.N);
+    }
+};
+
+static uint64_t fnv1a(const std::string& v) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char ch : v) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static TuneKey launch_class(const cwt_plan_s* p0, int hop_lo, int hop_hi, int64_t n_clips, int64_t mean_len) {
+    TuneKey k;
+    k.arch = p0->arch_hash;
+    k.cus = p0->cus;
+    k.dt = p0->dt;
+    k.S = (int)p0->bank->scales.size();
+    k.Mb = log2_bucket(std::max(1, p0->bank->Mmax));
+    k.hlo = log2_bucket(hop_lo);
+    k.hhi = log2_bucket(hop_hi);
+    k.C = log2_bucket(std::max<int64_t>(1, n_clips));
+    k.N = log2_bucket(std::max<int64_t>(1, mean_len));
+    return k;
 }
 
 static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tuned;   // launch class -> configuration
+static bool g_tuned_loaded = false;
+static std::atomic<int> g_tuned_count{0};   // entries of g_tuned (a lock-free "none" test)
 
-static std::map<std::string, int> read_tune_cache() {
-    std::map<std::string, int> m;
+// Cache file lines: "<arch hash hex>/<cus>/dt<d>/S<s>/M<m>/h<lo>-<hi>/C<c>/N<n>": <configuration>
+static void load_tuned_locked() {
+    if (g_tuned_loaded) return;
+    g_tuned_loaded = true;
     const char* path = std::getenv("CWTH_AUTOTUNE_CACHE");
-    if (!path) return m;
+    if (!path) return;
     std::ifstream f(path);
-    if (!f) return m;
+    if (!f) return;
     std::string line;
-    // Format: one "key": index pair per line inside a JSON object.
     while (std::getline(f, line)) {
-        size_t a = line.find('"');
-        size_t b = line.find('"', a + 1);
-        size_t c = line.find(':', b + 1);
-        if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
-        m[line.substr(a + 1, b - a - 1)] = std::atoi(line.c_str() + c + 1);
+        unsigned long long arch = 0;
+        TuneKey k;
+        int v = -1;
+        if (std::sscanf(line.c_str(), " \"%llx/%d/dt%d/S%d/M%d/h%d-%d/C%d/N%d\": %d", &arch, &k.cus, &k.dt, &k.S,
+                        &k.Mb, &k.hlo, &k.hhi, &k.C, &k.N, &v) != 10)
+            continue;
+        k.arch = arch;
+        if (v >= 0 && v < kNumMfmaCfgs) g_tuned[k] = v;
     }
-    return m;
+    g_tuned_count = (int)g_tuned.size();
 }
 
-static void write_tune_cache(const std::map<std::string, int>& m) {
+static void save_tuned_locked() {
     const char* path = std::getenv("CWTH_AUTOTUNE_CACHE");
     if (!path) return;
     std::string tmp = std::string(path) + ".tmp";
@@ -479,10 +527,33 @@ static void write_tune_cache(const std::map<std::string, int>& m) {
     if (!f) return;
     f << "{\n";
     size_t i = 0;
-    for (auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    for (auto& kv : g_tuned) {
+        const TuneKey& k = kv.first;
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "  \"%llx/%d/dt%d/S%d/M%d/h%d-%d/C%d/N%d\": %d", (unsigned long long)k.arch,
+                      k.cus, k.dt, k.S, k.Mb, k.hlo, k.hhi, k.C, k.N, kv.second);
+        f << buf << (++i < g_tuned.size() ? ",\n" : "\n");
+    }
     f << "}\n";
     f.close();
     std::rename(tmp.c_str(), path);
+}
+
+static void ensure_tuned_loaded() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tuned_locked();
+    });
+}
+
+// The tuned configuration of a launch class, or -1.
+static int tuned_lookup(const TuneKey& cls) {
+    ensure_tuned_loaded();
+    if (g_tuned_count.load(std::memory_order_relaxed) == 0) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(cls);
+    return it == g_tuned.end() ? -1 : it->second;
 }
 
 // Default configuration by hop (measured on MI355X, 128 linear scales, 10 s
@@ -626,6 +697,43 @@ static int auto_cfg(const cwt_plan_s* p, WG&& wgs) {
         if (i == 2 || wgs(L) >= need) return kAutoCfgs[i];
     }
     return p->cfg;
+}
+
+// The per-launch choice for a launch of n clips (one clip: cwt_execute's).
+static int batch_auto_cfg(const cwt_plan_t* plans, const int64_t* lens, int n) {
+    return auto_cfg(plans[0], [&](const ClipLayout& L) {
+        int64_t t = 0;
+        for (int i = 0; i < n; ++i) {
+            const int64_t K = (lens[i] + plans[i]->hop - 1) / plans[i]->hop;
+            t += (K + L.F - 1) / L.F * L.groups;
+        }
+        return t;
+    });
+}
+
+// A tuned configuration for this launch (see launch_class), or `cfg` when
+// none is recorded, the plan's configuration was set by the caller, or the
+// tuned one does not fit one of the launch's hops.
+static int with_tuned(const cwt_plan_t* plans, const int64_t* lens, int n, int cfg) {
+    const cwt_plan_s* p0 = plans[0];
+    if (p0->cfg_user || p0->dt == DT_FP32) return cfg;
+    ensure_tuned_loaded();
+    if (g_tuned_count.load(std::memory_order_relaxed) == 0) return cfg;
+    int hlo = p0->hop, hhi = p0->hop, cnt = 0;
+    int64_t sum = 0;
+    for (int i = 0; i < n; ++i) {
+        if (lens[i] <= 0) continue;
+        hlo = std::min(hlo, plans[i]->hop);
+        hhi = std::max(hhi, plans[i]->hop);
+        sum += lens[i];
+        ++cnt;
+    }
+    if (cnt == 0) return cfg;
+    const int t = tuned_lookup(launch_class(p0, hlo, hhi, cnt, sum / cnt));
+    if (t < 0) return cfg;
+    for (int i = 0; i < n; ++i)
+        if (lens[i] > 0 && !cfg_fits(plans[i], t, plans[i]->hop)) return cfg;
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -795,13 +903,30 @@ static int persistent_grid(int cus, int dt, int A, int kind, int64_t lds_bytes, 
     return g;
 }
 
-static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float* const* xs,
-                            const int64_t* lens, float* const* outs, int32_t n, int use_graph,
-                            hipStream_t stream) {
-    if (n < 0) return fail(CWT_ERR_INVALID_ARG, "n < 0");
-    if (n == 0) return CWT_OK;
+// Everything a persistent batch launch needs, computed on the host from the
+// batch alone (batch_prepare); the descriptors themselves go to a caller's
+// host buffer, laid out as [int32 nclips, int32 total_tiles, pad to 16]
+// [ClipArg x nc] [int32 prefix x (nc+1)], nc = clips with len > 0.
+struct BatchLaunch {
+    bool fp32 = false;
+    int nc = 0;              // clips in the launch (len > 0), longest first
+    int64_t total = 0;       // tiles over all clips
+    size_t used_bytes = 0;   // descriptor bytes
+    int dt = 0, A = 1, pkind = 0, grid = 0;
+    MfmaArgs a;              // clips / tile_prefix filled in by batch_launch
+    DirectArgs d;
+};
+
+// Host scratch batch_prepare needs for n clips: order[n], clips[n], ctiles[n].
+struct BatchScratch {
+    int* order;
+    ClipArg* clips;
+    int64_t* ctiles;
+};
+
+static cwt_status batch_validate(const cwt_plan_t* plans, const float* const* xs, const int64_t* lens,
+                                 float* const* outs, int32_t n) {
     if (!plans || !xs || !lens || !outs) return fail(CWT_ERR_INVALID_ARG, "NULL batch array");
-    if (n > b->max_clips) return fail(CWT_ERR_INVALID_ARG, "batch larger than the context's max_clips");
     const cwt_plan_s* p0 = plans[0];
     if (!p0) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
     for (int i = 0; i < n; ++i) {
@@ -815,7 +940,16 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         if (K > 0 && (int64_t)p->bank->scales.size() > INT64_MAX / K)
             return fail(CWT_ERR_INVALID_ARG, "output size overflows int64");
     }
-    if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
+    return CWT_OK;
+}
+
+// Configuration, chunk, per-clip records (longest first) and launch geometry
+// of a validated batch; descriptors written to `host` (host_cap bytes).  No
+// device work and no heap allocation beyond what the caller passes in.
+static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs, const int64_t* lens,
+                                float* const* outs, int32_t n, int cus, int force_cfg, const BatchScratch& sc,
+                                uint8_t* host, size_t host_cap, BatchLaunch* bl) {
+    const cwt_plan_s* p0 = plans[0];
     const Bank& bk = *p0->bank;
 
     // One configuration for the whole launch (the first plan's) and one chunk
@@ -823,14 +957,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     // LDS (operand buffers plus raw window) fits the budget.  WIN and SPLIT
     // clips have a fixed geometry per (bank, hop, configuration).
     const bool fp32 = p0->dt == DT_FP32;
-    int cfg = auto_cfg(p0, [&](const ClipLayout& L) {
-        int64_t t = 0;
-        for (int i = 0; i < n; ++i) {
-            const int64_t K = (lens[i] + plans[i]->hop - 1) / plans[i]->hop;
-            t += (K + L.F - 1) / L.F * L.groups;
-        }
-        return t;
-    });
+    int cfg = force_cfg >= 0 ? force_cfg : with_tuned(plans, lens, n, batch_auto_cfg(plans, lens, n));
     MfmaCfg c = kMfmaCfgs[fp32 ? 0 : cfg];
     bool cached_ok = true;   // plans[i]->lay is valid for this launch when plans[i]->cfg == cfg
     int chunk = 8;
@@ -884,22 +1011,19 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     }
     const SplitGeo sg = fp32 ? SplitGeo{1, 32, 8, 1} : split_geo(p0->dt, (int)bk.blocks.size());
 
-    // Wait until the pinned buffer we are about to overwrite has been consumed.
-    const int slot = b->flip;
-    b->flip ^= 1;
-    if (b->used[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch reuse wait");
-    uint8_t* host = b->pinned[slot];
-    std::vector<int> order;
+    int nc = 0;
     for (int i = 0; i < n; ++i)
-        if (lens[i] > 0) order.push_back(i);
+        if (lens[i] > 0) sc.order[nc++] = i;
+    bl->fp32 = fp32;
+    bl->nc = nc;
+    if (nc == 0) return CWT_OK;
     // Longest first (most tiles first) so the persistent grid drains evenly.
-    std::vector<ClipArg> clips(n);
-    std::vector<int64_t> ctiles(n, 0);
     int64_t maxbuf = 16, maxraw = 0, maxwin = 0;
-    for (int i : order) {
+    for (int j = 0; j < nc; ++j) {
+        const int i = sc.order[j];
         ClipLayout L;
-        clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], c, cached_ok && plans[i]->cfg == cfg, chunk, &L,
-                             &ctiles[i]);
+        sc.clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], c, cached_ok && plans[i]->cfg == cfg, chunk, &L,
+                                &sc.ctiles[i]);
         if (fp32) continue;
         if (L.s.mode == STAGE_WIN) {
             maxwin = std::max(maxwin, L.s.bytes);
@@ -908,22 +1032,109 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
             maxraw = std::max(maxraw, L.s.raw_bytes);
         }
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int bq) { return ctiles[a] > ctiles[bq]; });
-    const int nc = (int)order.size();
-    if (nc == 0) return CWT_OK;
+    // (most tiles first, then input order: what a stable sort gives, without
+    // its temporary buffer)
+    std::sort(sc.order, sc.order + nc, [&](int a, int bq) {
+        return sc.ctiles[a] != sc.ctiles[bq] ? sc.ctiles[a] > sc.ctiles[bq] : a < bq;
+    });
+    const size_t used_bytes = 16 + sizeof(ClipArg) * nc + sizeof(int32_t) * (nc + 1);
+    if (used_bytes > host_cap) return fail(CWT_ERR_INTERNAL, "descriptor buffer too small");
     ClipArg* hc = (ClipArg*)(host + 16);
     int32_t* hp = (int32_t*)(host + 16 + sizeof(ClipArg) * nc);
     int64_t total = 0;
     for (int j = 0; j < nc; ++j) {
-        hc[j] = clips[order[j]];
+        hc[j] = sc.clips[sc.order[j]];
         hp[j] = (int32_t)total;
-        total += ctiles[order[j]];
+        total += sc.ctiles[sc.order[j]];
         if (total > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "batch has too many tiles");
     }
     hp[nc] = (int32_t)total;
+    std::memset(host, 0, 16);
     ((int32_t*)host)[0] = nc;
     ((int32_t*)host)[1] = (int32_t)total;
-    const size_t used_bytes = 16 + sizeof(ClipArg) * nc + sizeof(int32_t) * (nc + 1);
+    bl->total = total;
+    bl->used_bytes = used_bytes;
+    bl->dt = p0->dt;
+    bl->A = c.A;
+
+    if (fp32) {
+        std::memset(&bl->d, 0, sizeof(bl->d));
+        bl->d.taps = bk.d_dtaps;
+        bl->d.groups = bk.d_dgroups;
+        bl->d.ngroups = (int)bk.dgroups.size();
+        bl->d.signed_out = p0->signed_out;
+        return CWT_OK;
+    }
+    MfmaArgs& a = bl->a;
+    std::memset(&a, 0, sizeof(a));
+    a.frags = bk.d_frags;
+    a.blocks = bk.d_blocks;
+    a.ngroups = (int)bk.blocks.size();
+    a.signed_out = p0->signed_out;
+    a.chunk_steps = chunk;
+    a.frames = 128 * c.A;
+    a.split_wb = sg.wb;
+    a.split_chunk = sg.chunk;
+    a.buf_bytes = (int32_t)maxbuf;
+    a.raw_bytes = (int32_t)maxraw;
+    a.shm_bytes = (int32_t)std::max(2 * maxbuf + maxraw, maxwin);
+    a.xcd_remap = 0;
+    a.nclips = nc;
+    a.total_tiles = (int32_t)total;
+    // WIN-only batches run the kernel compiled for the WIN register budget.
+    bool win_only = true;
+    for (int j = 0; j < nc; ++j) win_only = win_only && hc[j].mode == STAGE_WIN;
+    bl->pkind = win_only ? 2 : 1;
+    int64_t groups_lcm = 1;
+    for (int j = 0; j < nc; ++j) {
+        const int64_t ng = hc[j].mode == STAGE_WIN ? (a.ngroups + hc[j].wb - 1) / hc[j].wb
+                           : hc[j].mode == STAGE_LINEAR ? a.ngroups : sg.groups;
+        groups_lcm = groups_lcm / gcd64(groups_lcm, ng) * ng;
+        if (groups_lcm > 4096) groups_lcm = 4096;   // bounded: a heuristic, not a requirement
+    }
+    bl->grid = (int)std::min<int64_t>(persistent_grid(cus, p0->dt, c.A, bl->pkind, a.shm_bytes, groups_lcm), total);
+    return CWT_OK;
+}
+
+// Point a prepared launch at descriptors resident at device address dd.
+static void batch_bind(BatchLaunch* bl, const uint8_t* dd) {
+    bl->a.clips = (const ClipArg*)(dd + 16);
+    bl->a.tile_prefix = (const int32_t*)(dd + 16 + sizeof(ClipArg) * bl->nc);
+}
+
+// The persistent launch (or the plain path's flat launch) of a prepared and
+// bound batch whose descriptors are in device memory at dd.
+static hipError_t batch_launch(const BatchLaunch& bl, const uint8_t* dd, hipStream_t stream) {
+    if (bl.fp32)
+        return launch_direct_batch(bl.d, (const ClipArg*)(dd + 16), (const int32_t*)(dd + 16 + sizeof(ClipArg) * bl.nc),
+                                   bl.nc, (int)bl.total, stream);
+    return launch_mfma(bl.dt, bl.A, 1, bl.a, bl.pkind, bl.grid, stream);
+}
+
+static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float* const* xs,
+                            const int64_t* lens, float* const* outs, int32_t n, int use_graph,
+                            hipStream_t stream, int force_cfg = -1) {
+    if (n < 0) return fail(CWT_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return CWT_OK;
+    if (n > b->max_clips) return fail(CWT_ERR_INVALID_ARG, "batch larger than the context's max_clips");
+    cwt_status st = batch_validate(plans, xs, lens, outs, n);
+    if (st != CWT_OK) return st;
+    const cwt_plan_s* p0 = plans[0];
+    if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
+
+    // Wait until the pinned buffer we are about to overwrite has been consumed.
+    const int slot = b->flip;
+    b->flip ^= 1;
+    if (b->used[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch reuse wait");
+    uint8_t* host = b->pinned[slot];
+    std::vector<int> order(n);
+    std::vector<ClipArg> clips(n);
+    std::vector<int64_t> ctiles(n, 0);
+    BatchLaunch bl;
+    st = batch_prepare(plans, xs, lens, outs, n, b->cus, force_cfg, BatchScratch{order.data(), clips.data(), ctiles.data()},
+                       host, b->desc_cap, &bl);
+    if (st != CWT_OK || bl.nc == 0) return st;
+    const size_t used_bytes = bl.used_bytes;
 
     // Device descriptors: reuse the buffer that already holds exactly these
     // (a prepared batch run again: no upload); otherwise overwrite the other
@@ -941,6 +1152,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
     }
     uint8_t* const dd = b->d_desc[ds];
+    batch_bind(&bl, dd);
     auto finish = [&]() -> cwt_status {
         HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
         HIP_TRY(hipEventRecord(b->ddone[ds], stream), "descriptor event");
@@ -950,107 +1162,64 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         return CWT_OK;
     };
 
-    if (fp32) {
-        // The plain path: descriptor upload and one flat launch over every tile.
-        DirectArgs d;
-        std::memset(&d, 0, sizeof(d));
-        d.taps = bk.d_dtaps;
-        d.groups = bk.d_dgroups;
-        d.ngroups = (int)bk.dgroups.size();
-        d.signed_out = p0->signed_out;
+    if (bl.fp32 || !use_graph) {
+        // descriptor upload (unless resident) and one launch
         if (upload) HIP_TRY(hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
-        HIP_TRY(launch_direct_batch(d, (const ClipArg*)(dd + 16), (const int32_t*)(dd + 16 + sizeof(ClipArg) * nc), nc,
-                                    (int)total, stream), "direct batch launch");
+        HIP_TRY(batch_launch(bl, dd, stream), bl.fp32 ? "direct batch launch" : "persistent launch");
         return finish();
     }
-    MfmaArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.frags = bk.d_frags;
-    a.blocks = bk.d_blocks;
-    a.ngroups = (int)bk.blocks.size();
-    a.signed_out = p0->signed_out;
-    a.chunk_steps = chunk;
-    a.frames = 128 * c.A;
-    a.split_wb = sg.wb;
-    a.split_chunk = sg.chunk;
-    a.buf_bytes = (int32_t)maxbuf;
-    a.raw_bytes = (int32_t)maxraw;
-    a.shm_bytes = (int32_t)std::max(2 * maxbuf + maxraw, maxwin);
-    a.xcd_remap = 0;
-    // The descriptor pointers are fixed device addresses; counts live in the header.
-    a.clips = (const ClipArg*)(dd + 16);
-    a.tile_prefix = (const int32_t*)(dd + 16 + sizeof(ClipArg) * nc);
-    a.nclips = nc;
-    a.total_tiles = (int32_t)total;
-    // WIN-only batches run the kernel compiled for the WIN register budget.
-    bool win_only = true;
-    for (int j = 0; j < nc; ++j) win_only = win_only && hc[j].mode == STAGE_WIN;
-    const int pkind = win_only ? 2 : 1;
-    int64_t groups_lcm = 1;
-    for (int j = 0; j < nc; ++j) {
-        const int64_t ng = hc[j].mode == STAGE_WIN ? (a.ngroups + hc[j].wb - 1) / hc[j].wb
-                           : hc[j].mode == STAGE_LINEAR ? a.ngroups : sg.groups;
-        groups_lcm = groups_lcm / gcd64(groups_lcm, ng) * ng;
-        if (groups_lcm > 4096) groups_lcm = 4096;   // bounded: a heuristic, not a requirement
-    }
-    const int grid = (int)std::min<int64_t>(persistent_grid(b->cus, p0->dt, c.A, pkind, a.shm_bytes, groups_lcm),
-                                            total);
-
-    if (!use_graph) {
-        if (upload) HIP_TRY(hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, stream), "descriptor upload");
-        HIP_TRY(launch_mfma(p0->dt, c.A, 1, a, pkind, grid, stream), "persistent launch");
-    } else {
-        // One graph per (shape, pinned buffer, device buffer, with or without
-        // the upload): the copy's source and destination are then fixed, and
-        // its size and the kernel arguments (counts, chunk) are refreshed only
-        // when they differ from the previous replay.
-        auto key = std::make_tuple(p0->dt, c.A, (int)a.shm_bytes, grid, pkind, 4 * slot + 2 * ds + (upload ? 1 : 0));
-        GraphEntry& ge = b->graphs[key];
-        if (!ge.exec) {
-            HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-            hipError_t e1 = upload ? hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream)
-                                   : hipSuccess;
-            hipError_t e2 = launch_mfma(p0->dt, c.A, 1, a, pkind, grid, b->cap_stream);
-            hipGraph_t g = nullptr;
-            hipError_t e3 = hipStreamEndCapture(b->cap_stream, &g);
-            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                b->graphs.erase(key);
-                return fail(CWT_ERR_DEVICE, "graph capture failed");
-            }
-            ge.graph = g;
-            size_t nn = 0;
-            HIP_TRY(hipGraphGetNodes(g, nullptr, &nn), "graph nodes");
-            std::vector<hipGraphNode_t> nodes(nn);
-            HIP_TRY(hipGraphGetNodes(g, nodes.data(), &nn), "graph nodes");
-            for (auto nd : nodes) {
-                hipGraphNodeType t;
-                HIP_TRY(hipGraphNodeGetType(nd, &t), "graph node type");
-                if (t == hipGraphNodeTypeMemcpy) ge.copy_node = nd;
-                if (t == hipGraphNodeTypeKernel) ge.kernel_node = nd;
-            }
-            if ((upload && !ge.copy_node) || !ge.kernel_node) return fail(CWT_ERR_INTERNAL, "unexpected graph shape");
-            HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0), "graph instantiate");
-            std::memcpy(&ge.args, &a, sizeof(a));   // padding included, for the memcmp below
-            ge.copy_bytes = used_bytes;
-        } else {
-            if (upload && ge.copy_bytes != used_bytes) {
-                HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, dd, host, used_bytes,
-                                                          hipMemcpyHostToDevice), "graph copy update");
-                ge.copy_bytes = used_bytes;
-            }
-            if (std::memcmp(&ge.args, &a, sizeof(a)) != 0) {
-                hipKernelNodeParams kp;
-                HIP_TRY(hipGraphKernelNodeGetParams(ge.kernel_node, &kp), "kernel node params");
-                void* args[1] = {&a};
-                kp.kernelParams = args;
-                kp.extra = nullptr;
-                HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.kernel_node, &kp), "kernel node update");
-                std::memcpy(&ge.args, &a, sizeof(a));
-            }
+    const MfmaArgs& a = bl.a;
+    // One graph per (shape, pinned buffer, device buffer, with or without
+    // the upload): the copy's source and destination are then fixed, and
+    // its size and the kernel arguments (counts, chunk) are refreshed only
+    // when they differ from the previous replay.
+    auto key = std::make_tuple(bl.dt, bl.A, (int)a.shm_bytes, bl.grid, bl.pkind, 4 * slot + 2 * ds + (upload ? 1 : 0));
+    GraphEntry& ge = b->graphs[key];
+    if (!ge.exec) {
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t e1 = upload ? hipMemcpyAsync(dd, host, used_bytes, hipMemcpyHostToDevice, b->cap_stream)
+                               : hipSuccess;
+        hipError_t e2 = batch_launch(bl, dd, b->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e3 = hipStreamEndCapture(b->cap_stream, &g);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            b->graphs.erase(key);
+            return fail(CWT_ERR_DEVICE, "graph capture failed");
         }
-        HIP_TRY(hipGraphLaunch(ge.exec, stream), "graph launch");
+        ge.graph = g;
+        size_t nn = 0;
+        HIP_TRY(hipGraphGetNodes(g, nullptr, &nn), "graph nodes");
+        std::vector<hipGraphNode_t> nodes(nn);
+        HIP_TRY(hipGraphGetNodes(g, nodes.data(), &nn), "graph nodes");
+        for (auto nd : nodes) {
+            hipGraphNodeType t;
+            HIP_TRY(hipGraphNodeGetType(nd, &t), "graph node type");
+            if (t == hipGraphNodeTypeMemcpy) ge.copy_node = nd;
+            if (t == hipGraphNodeTypeKernel) ge.kernel_node = nd;
+        }
+        if ((upload && !ge.copy_node) || !ge.kernel_node) return fail(CWT_ERR_INTERNAL, "unexpected graph shape");
+        HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0), "graph instantiate");
+        std::memcpy(&ge.args, &a, sizeof(a));   // padding included, for the memcmp below
+        ge.copy_bytes = used_bytes;
+    } else {
+        if (upload && ge.copy_bytes != used_bytes) {
+            HIP_TRY(hipGraphExecMemcpyNodeSetParams1D(ge.exec, ge.copy_node, dd, host, used_bytes,
+                                                      hipMemcpyHostToDevice), "graph copy update");
+            ge.copy_bytes = used_bytes;
+        }
+        if (std::memcmp(&ge.args, &a, sizeof(a)) != 0) {
+            hipKernelNodeParams kp;
+            HIP_TRY(hipGraphKernelNodeGetParams(ge.kernel_node, &kp), "kernel node params");
+            MfmaArgs ak = a;
+            void* args[1] = {&ak};
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.kernel_node, &kp), "kernel node update");
+            std::memcpy(&ge.args, &a, sizeof(a));
+        }
     }
+    HIP_TRY(hipGraphLaunch(ge.exec, stream), "graph launch");
     return finish();
 }
 
@@ -1105,6 +1274,7 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
         p->device = dev;
         p->cus = di.cus;
         p->arch = di.arch;
+        p->arch_hash = fnv1a(di.arch);
         st = acquire_bank(p->dt, dev, sc, &p->bank);
         if (st != CWT_OK) return st;
         {
@@ -1114,18 +1284,8 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
             if (ae != hipSuccess) return fail(CWT_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(ae));
         }
         set_cfg(p.get(), default_cfg(p.get(), hop));
-        bool tuned = false;
-        {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto m = read_tune_cache();
-            // the length bucket of 10 s at 16 kHz is the default class
-            auto it = m.find(tune_key(p.get(), 160000));
-            if (it != m.end() && cfg_fits(p.get(), it->second, hop)) {
-                set_cfg(p.get(), it->second);
-                tuned = true;
-            }
-        }
-        if (!tuned && p->cfg == 6) set_auto(p.get());
+        if (p->cfg == 6) set_auto(p.get());
+        ensure_tuned_loaded();   // here, so that no launch reads the cache file
         // an automatic plan's 6 stands for the per-launch choice (auto_cfg)
         if (!p->cfg_auto && !cfg_fits(p.get(), p->cfg, hop)) {
             bool found = false;
@@ -1184,7 +1344,8 @@ cwt_status cwt_execute(cwt_plan_t plan, const float* x, int64_t len, float* out,
         int64_t K = (len + plan->hop - 1) / plan->hop;
         if ((int64_t)plan->bank->scales.size() > INT64_MAX / K)
             return fail(CWT_ERR_INVALID_ARG, "output size overflows int64");
-        const int cfg = auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups; });
+        int cfg = auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups; });
+        cfg = with_tuned(&plan, &len, 1, cfg);
         return launch_one(plan, cfg, x, len, out, (hipStream_t)stream);
     } catch (...) {
         return fail(CWT_ERR_INTERNAL, "unexpected exception");
@@ -1258,7 +1419,10 @@ int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips) {
     if (!plan || len < 1 || n_clips < 1) return -1;
     if (plan->dt == DT_FP32) return plan->cfg;
     const int64_t K = (len + plan->hop - 1) / plan->hop;
-    return auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups * n_clips; });
+    const int cfg = auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups * n_clips; });
+    std::vector<cwt_plan_t> pl(n_clips, plan);
+    std::vector<int64_t> ln(n_clips, len);
+    return with_tuned(pl.data(), ln.data(), n_clips, cfg);
 }
 int32_t cwt_plan_num_configs(cwt_plan_t plan) {
     if (!plan) return -1;
@@ -1269,61 +1433,151 @@ cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index) {
     if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
     if (!cfg_fits(plan, index, plan->hop)) return fail(CWT_ERR_INVALID_ARG, "configuration does not fit this plan");
     set_cfg(plan, index);
+    plan->cfg_user = true;
     return CWT_OK;
 }
 
-cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out) {
+cwt_status cwt_autotune_batch(const cwt_plan_t* plans, const int64_t* lens, int32_t n, int32_t* chosen_out) {
     try {
-        if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
-        if (len < 1) return fail(CWT_ERR_INVALID_ARG, "len must be >= 1");
-        const int64_t K = (len + plan->hop - 1) / plan->hop;
-        const int64_t S = (int64_t)plan->bank->scales.size();
+        if (n < 1 || !plans || !lens) return fail(CWT_ERR_INVALID_ARG, "need n >= 1 plans and lengths");
+        const cwt_plan_s* p0 = plans[0];
+        if (!p0) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+        int64_t total_x = 0, total_out = 0, sum = 0;
+        int hlo = p0->hop, hhi = p0->hop;
+        for (int i = 0; i < n; ++i) {
+            if (!plans[i]) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+            if (plans[i]->bank != p0->bank || plans[i]->signed_out != p0->signed_out)
+                return fail(CWT_ERR_UNSUPPORTED, "batch plans differ in dtype, scales or output mode");
+            if (lens[i] < 1) return fail(CWT_ERR_INVALID_ARG, "lengths must be >= 1");
+            const int64_t K = (lens[i] + plans[i]->hop - 1) / plans[i]->hop;
+            total_x += lens[i];
+            total_out += (int64_t)p0->bank->scales.size() * K;
+            sum += lens[i];
+            hlo = std::min(hlo, plans[i]->hop);
+            hhi = std::max(hhi, plans[i]->hop);
+        }
+        int dev = 0;
+        cwt_status st = current_device(&dev, nullptr);
+        if (st != CWT_OK) return st;
+        if (p0->device != dev) return fail(CWT_ERR_INVALID_ARG, "plans belong to another device");
+        if (p0->dt == DT_FP32) {   // one configuration: nothing to tune
+            if (chosen_out) *chosen_out = p0->cfg;
+            return CWT_OK;
+        }
+        // a seeded noise signal (the kernels' cost does not depend on the values)
+        std::vector<float> hx((size_t)std::min<int64_t>(total_x, 1 << 20));
+        uint32_t r = 1430200u;
+        for (auto& v : hx) {
+            r = r * 1664525u + 1013904223u;
+            v = (float)((int32_t)r) * (1.0f / 2147483648.0f);
+        }
         float *x = nullptr, *out = nullptr;
-        HIP_TRY(hipMalloc(&x, sizeof(float) * len), "autotune input");
-        std::unique_ptr<float, void (*)(float*)> gx(x, [](float* p) { (void)hipFree(p); });
-        HIP_TRY(hipMalloc(&out, sizeof(float) * S * K), "autotune output");
-        std::unique_ptr<float, void (*)(float*)> go(out, [](float* p) { (void)hipFree(p); });
-        HIP_TRY(hipMemset(x, 0, sizeof(float) * len), "autotune input init");
+        HIP_TRY(hipMalloc(&x, sizeof(float) * total_x), "autotune input");
+        std::unique_ptr<float, void (*)(float*)> gx(x, [](float* q) { (void)hipFree(q); });
+        HIP_TRY(hipMalloc(&out, sizeof(float) * total_out), "autotune output");
+        std::unique_ptr<float, void (*)(float*)> go(out, [](float* q) { (void)hipFree(q); });
+        for (int64_t o = 0; o < total_x; o += (int64_t)hx.size())
+            HIP_TRY(hipMemcpy(x + o, hx.data(), sizeof(float) * std::min<int64_t>(hx.size(), total_x - o),
+                              hipMemcpyHostToDevice), "autotune input upload");
+        std::vector<const float*> xs(n);
+        std::vector<float*> outs(n);
+        {
+            int64_t ox = 0, oo = 0;
+            for (int i = 0; i < n; ++i) {
+                xs[i] = x + ox;
+                outs[i] = out + oo;
+                ox += lens[i];
+                oo += (int64_t)p0->bank->scales.size() * ((lens[i] + plans[i]->hop - 1) / plans[i]->hop);
+            }
+        }
+        std::unique_ptr<cwt_batch_s> bctx;
+        if (n > 1) {
+            bctx = std::make_unique<cwt_batch_s>();
+            st = batch_init(bctx.get(), n);
+            if (st != CWT_OK) return st;
+        }
+        hipStream_t sm = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&sm, hipStreamNonBlocking), "autotune stream");
+        std::unique_ptr<void, void (*)(void*)> gs(sm, [](void* q) { (void)hipStreamDestroy((hipStream_t)q); });
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0), "event");
         HIP_TRY(hipEventCreate(&e1), "event");
-        int best = plan->cfg;
-        float best_ms = 1e30f;
-        const int ncfg = cwt_plan_num_configs(plan);
-        for (int c = 0; c < ncfg; ++c) {
-            if (!cfg_fits(plan, c, plan->hop)) continue;
+        std::unique_ptr<void, void (*)(void*)> ge0(e0, [](void* q) { (void)hipEventDestroy((hipEvent_t)q); });
+        std::unique_ptr<void, void (*)(void*)> ge1(e1, [](void* q) { (void)hipEventDestroy((hipEvent_t)q); });
+        // the automatic choice for this launch (what runs without tuning)
+        const int auto_choice = batch_auto_cfg(plans, lens, n);
+        auto run = [&](int cfg) -> cwt_status {
+            if (n == 1) return launch_one(p0, cfg, xs[0], lens[0], outs[0], sm);
+            return batch_run(bctx.get(), plans, xs.data(), lens, outs.data(), n, 0, sm, cfg);
+        };
+        // mean of timed launches after two untimed ones, >= 5 launches and
+        // >= 20 ms of device time
+        auto time_cfg = [&](int cfg, float* ms_out) -> cwt_status {
             for (int w = 0; w < 2; ++w) {
-                cwt_status st = launch_one(plan, c, x, len, out, 0);
-                if (st != CWT_OK) return st;
+                cwt_status s2 = run(cfg);
+                if (s2 != CWT_OK) return s2;
             }
-            const int reps = 10;
-            HIP_TRY(hipEventRecord(e0, 0), "event");
-            for (int r = 0; r < reps; ++r) {
-                cwt_status st = launch_one(plan, c, x, len, out, 0);
-                if (st != CWT_OK) return st;
+            int reps = 5;
+            for (;;) {
+                HIP_TRY(hipEventRecord(e0, sm), "event");
+                for (int q = 0; q < reps; ++q) {
+                    cwt_status s2 = run(cfg);
+                    if (s2 != CWT_OK) return s2;
+                }
+                HIP_TRY(hipEventRecord(e1, sm), "event");
+                HIP_TRY(hipEventSynchronize(e1), "event");
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
+                if (ms >= 20.0f || reps >= 4096) {
+                    *ms_out = ms / reps;
+                    return CWT_OK;
+                }
+                reps *= 4;
             }
-            HIP_TRY(hipEventRecord(e1, 0), "event");
-            HIP_TRY(hipEventSynchronize(e1), "event");
+        };
+        // candidates: the automatic choice, then every configuration that
+        // fits every clip's hop
+        float auto_ms = 0;
+        st = time_cfg(auto_choice, &auto_ms);
+        if (st != CWT_OK) return st;
+        int best = -1;
+        float best_ms = auto_ms;
+        for (int c = 0; c < kNumMfmaCfgs; ++c) {
+            bool ok = true;
+            for (int i = 0; i < n && ok; ++i) ok = cfg_fits(plans[i], c, plans[i]->hop);
+            if (!ok) continue;
             float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
+            st = time_cfg(c, &ms);
+            if (st != CWT_OK) return st;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = c;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        set_cfg(plan, best);
-        if (chosen_out) *chosen_out = best;
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto m = read_tune_cache();
-        m[tune_key(plan, len)] = best;
-        m[tune_key(plan, 160000)] = best;
-        write_tune_cache(m);
+        HIP_TRY(hipStreamSynchronize(sm), "autotune sync");
+        const TuneKey cls = launch_class(p0, hlo, hhi, n, sum / n);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            load_tuned_locked();
+            if (best >= 0 && best_ms < (1.0 - kTuneMargin) * auto_ms)
+                g_tuned[cls] = best;
+            else
+                g_tuned.erase(cls);
+            g_tuned_count = (int)g_tuned.size();
+            save_tuned_locked();
+        }
+        if (chosen_out) *chosen_out = with_tuned(plans, lens, n, auto_choice);
         return CWT_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(CWT_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
         return fail(CWT_ERR_INTERNAL, "unexpected exception");
     }
+}
+
+cwt_status cwt_autotune(cwt_plan_t plan, int64_t len, int32_t* chosen_out) {
+    if (!plan) return fail(CWT_ERR_INVALID_ARG, "NULL plan");
+    return cwt_autotune_batch(&plan, &len, 1, chosen_out);
 }
 
 int64_t cwt_image_workspace_bytes(void) { return image_workspace_bytes(); }

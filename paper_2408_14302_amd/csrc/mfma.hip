@@ -483,7 +483,11 @@ __device__ float tile_beta(const ClipArg& c, int F, int64_t k0, int glo, int ghi
     if (m == 0.0f) return 1.0f;
     int e;
     frexp(448.0 / (double)m, &e);     // 448/m = f * 2^e, f in [0.5, 1)
-    return (float)ldexp(1.0, e - 1);
+    // at most 2^126, a normal float whose reciprocal is normal too: a segment
+    // whose largest sample lies below ~5e-36 would otherwise get beta = inf
+    // (and 0 * inf = NaN for its zero samples); with the clamp its samples
+    // still scale to at most 448
+    return (float)ldexp(1.0, min(e - 1, 126));
 }
 
 // The FP8 tile scale.  Up to hop kFp8SegmentMaxHop: beta of the
@@ -746,7 +750,9 @@ __device__ __forceinline__ void store_rows(const RowMap<DT>& m, const f32x16& ac
     for (int v = 0; v < 16; ++v) {
         if (m.row[v] < 0) continue;
         float val = acc[v];
-        if constexpr (DT == DT_FP8) val = val * (m.scale[v] * inv_beta);
+        // both factors are powers of two: exact whenever the result is normal,
+        // also for a clip so faint that inv_beta sits at 2^-126
+        if constexpr (DT == DT_FP8) val = val * m.scale[v] * inv_beta;
         if (!signed_out) val = fabsf(val);
         __builtin_nontemporal_store(val, out + (int64_t)m.row[v] * K + k);
     }

@@ -38,6 +38,7 @@ _SIGS = {
     "cwt_batch_destroy": (_i32, [_vp]),
     "cwt_batch_execute": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp]),
     "cwt_autotune": (_i32, [_c_plan, _i64, ctypes.POINTER(_i32)]),
+    "cwt_autotune_batch": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "cwt_plan_config": (_i32, [_c_plan]),
     "cwt_plan_num_configs": (_i32, [_c_plan]),
     "cwt_plan_launch_config": (_i32, [_c_plan, _i64, _i32]),
@@ -85,6 +86,23 @@ def version() -> str:
 
 def status_string(st: int) -> str:
     return _lib.cwt_status_string(int(st)).decode()
+
+
+def _alloc_stream(stream):
+    """A context under which torch allocates for work queued on `stream`
+    (None: the current stream).  The caching allocator ties a block to the
+    stream it was allocated on; a buffer that a kernel on another stream
+    writes must belong to that stream, or its memory can be handed out again
+    while the kernel still runs."""
+    import contextlib
+    import torch
+    if stream is None:
+        return contextlib.nullcontext()
+    if isinstance(stream, int):
+        if stream == torch.cuda.current_stream().cuda_stream:
+            return contextlib.nullcontext()
+        return torch.cuda.stream(torch.cuda.ExternalStream(stream))
+    return torch.cuda.stream(stream)
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -182,6 +200,8 @@ class Plan:
         _check(_lib.cwt_plan_set_config(self._h, int(i)), "cwt_plan_set_config")
 
     def autotune(self, n: int) -> int:
+        """Tune the one-clip launch of n samples (cwt_autotune); returns the
+        configuration such launches now run."""
         c = _i32()
         _check(_lib.cwt_autotune(self._h, int(n), ctypes.byref(c)), "cwt_autotune")
         return int(c.value)
@@ -204,8 +224,12 @@ class Plan:
                                 _stream_ptr(stream)), "cwt_execute")
 
     def __call__(self, x, out=None, stream=None):
+        """Transform x on `stream` (default: the current stream).  x must be
+        ready on that stream (ordered after the work that produced it); a new
+        output is allocated for that stream."""
         if out is None:
-            out = self.output(x.numel(), device=x.device)
+            with _alloc_stream(stream):
+                out = self.output(x.numel(), device=x.device)
         self.execute(x, out, stream)
         return out
 
@@ -234,10 +258,24 @@ def _arrays(plans, xs, outs):
     return n, P, X, L, O
 
 
-def _outs_for(plans, xs):
+def _outs_for(plans, xs, stream=None):
     import torch
-    return [torch.empty((p.num_scales, p.num_frames(x.numel())), dtype=torch.float32, device=x.device)
-            for p, x in zip(plans, xs)]
+    with _alloc_stream(stream):
+        return [torch.empty((p.num_scales, p.num_frames(x.numel())), dtype=torch.float32, device=x.device)
+                for p, x in zip(plans, xs)]
+
+
+def autotune_batch(plans, lens) -> int:
+    """Tune the persistent launch of these plans and lengths
+    (cwt_autotune_batch); returns the configuration such launches now run."""
+    n = len(plans)
+    if n != len(lens) or n < 1:
+        raise ValueError("need as many lengths as plans, at least one")
+    P = (_vp * n)(*[p.handle.value for p in plans])
+    L = (_i64 * n)(*[int(v) for v in lens])
+    c = _i32()
+    _check(_lib.cwt_autotune_batch(P, L, n, ctypes.byref(c)), "cwt_autotune_batch")
+    return int(c.value)
 
 
 def execute_batch(plans, xs, outs=None, stream=None):
@@ -245,7 +283,7 @@ def execute_batch(plans, xs, outs=None, stream=None):
     for x in xs:
         _check_signal(x)
     if outs is None:
-        outs = _outs_for(plans, xs)
+        outs = _outs_for(plans, xs, stream)
     n, P, X, L, O = _arrays(plans, xs, outs)
     _check(_lib.cwt_execute_batch(P, X, L, O, n, _stream_ptr(stream)), "cwt_execute_batch")
     return outs
@@ -264,7 +302,7 @@ class Batch:
         for x in xs:
             _check_signal(x)
         if outs is None:
-            outs = _outs_for(plans, xs)
+            outs = _outs_for(plans, xs, stream)
         n, P, X, L, O = _arrays(plans, xs, outs)
         _check(_lib.cwt_batch_execute(self._h, P, X, L, O, n, 1 if graph else 0, _stream_ptr(stream)),
                "cwt_batch_execute")

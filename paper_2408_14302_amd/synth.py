@@ -27,13 +27,13 @@ def clip_seed(config: int, index: int) -> int:
     return SEED_BASE + 100 * int(config) + int(index)
 
 
-def make_clip(seed: int, n: int, fs: float = 16000.0, snr_db: float = 0.0) -> np.ndarray:
-    """One peak-normalised float32 clip of n samples."""
+def clip_parts(seed: int, n: int, fs: float = 16000.0, snr_db: float = 0.0):
+    """The two components make_clip(seed, n, fs, snr_db) mixes, in float64 and
+    before peak normalisation: (tone, noise), noise = g * pink already scaled
+    to the SNR."""
     n = int(n)
     if n < 0:
         raise ValueError("n must be >= 0")
-    if n == 0:
-        return np.zeros(0, dtype=np.float32)
     rng = np.random.Generator(np.random.PCG64(int(seed)))
     f0 = rng.uniform(50.0, 500.0)
     nh = int(rng.integers(1, 11))
@@ -50,13 +50,24 @@ def make_clip(seed: int, n: int, fs: float = 16000.0, snr_db: float = 0.0) -> np
     shape = np.zeros_like(f)
     shape[1:] = 1.0 / np.sqrt(f[1:])
     pink = np.fft.irfft(spec * shape, n=n)
-    p_tone = float(np.mean(tone * tone))
-    p_pink = float(np.mean(pink * pink))
+    p_tone = float(np.mean(tone * tone)) if n else 0.0
+    p_pink = float(np.mean(pink * pink)) if n else 0.0
     if p_pink > 0.0 and p_tone > 0.0:
         g = math.sqrt(p_tone / (p_pink * 10.0 ** (snr_db / 10.0)))
     else:
         g = 1.0
-    x = tone + g * pink
+    return tone, g * pink
+
+
+def make_clip(seed: int, n: int, fs: float = 16000.0, snr_db: float = 0.0) -> np.ndarray:
+    """One peak-normalised float32 clip of n samples."""
+    n = int(n)
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    if n == 0:
+        return np.zeros(0, dtype=np.float32)
+    tone, noise = clip_parts(seed, n, fs, snr_db)
+    x = tone + noise
     peak = float(np.max(np.abs(x)))
     if peak > 0.0:
         x = x / peak
@@ -69,27 +80,6 @@ def clip_params(seed: int):
     f0 = rng.uniform(50.0, 500.0)
     nh = int(rng.integers(1, 11))
     return f0, nh
-
-
-def achieved_snr_db(seed: int, n: int, fs: float = 16000.0, snr_db: float = 0.0) -> float:
-    """Re-draw the components of make_clip and measure the SNR they were mixed at."""
-    rng = np.random.Generator(np.random.PCG64(int(seed)))
-    f0 = rng.uniform(50.0, 500.0)
-    nh = int(rng.integers(1, 11))
-    phases = rng.uniform(0.0, 2.0 * math.pi, size=nh)
-    t = np.arange(n, dtype=np.float64) / fs
-    tone = np.zeros(n)
-    for k in range(1, nh + 1):
-        if k * f0 >= fs / 2.0:
-            break
-        tone += np.cos(2.0 * math.pi * k * f0 * t + phases[k - 1]) / k
-    white = rng.standard_normal(n)
-    f = np.fft.rfftfreq(n, d=1.0 / fs)
-    shape = np.zeros_like(f)
-    shape[1:] = 1.0 / np.sqrt(f[1:])
-    pink = np.fft.irfft(np.fft.rfft(white) * shape, n=n)
-    g = math.sqrt(np.mean(tone ** 2) / (np.mean(pink ** 2) * 10.0 ** (snr_db / 10.0)))
-    return 10.0 * math.log10(np.mean(tone ** 2) / np.mean((g * pink) ** 2))
 
 
 def batch_lengths(seed: int, count: int, lo: int = 16000, hi: int = 160000) -> np.ndarray:

@@ -16,6 +16,15 @@ import pytest
 #   fp8     e4m3, u = 2^-4: sigma ~ 4.8e-2                      -> 1.5e-1 / 2e-1
 TOL = {"fp32": (1e-5, 1e-4), "fp16": (2e-3, 2e-3), "bf16": (1e-2, 1e-2),
        "bf16x3": (5e-5, 5e-5), "fp8": (1.5e-1, 2e-1)}
+# FP8 on the measured workloads (generator clips, the whole scalogram, every
+# hop): the blanket bound above assumes |x| = 1 at every sample; these clips
+# have an RMS near 0.3, and the maxima grow with the coefficient count like
+# sqrt(2 ln n).  Measured on MI355X (bench.py --errors), all hops:
+#   1 s, 32 scales (5e5 coefficients):        rel-L2 1.6-1.7e-2, max-abs 0.057-0.082
+#   10 s, 128 scales, 3 clips (6e7):          rel-L2 1.28e-2,    max-abs 0.070-0.100
+#   8 x 60 s at 48 kHz, 256 geometric (4.6e7): rel-L2 1.46e-2,    max-abs 0.120-0.129
+# bounds: 2.5e-2 on rel-L2 and about 1.5x the largest measured max-abs.
+TOL_FP8_WORKLOAD = {"1s32": (2.5e-2, 0.12), "10s128": (2.5e-2, 0.15), "60s256": (2.5e-2, 0.2)}
 DTYPES = ("fp32", "bf16", "fp16", "bf16x3", "fp8")
 
 
@@ -43,10 +52,18 @@ def gain(scales, xmax=1.0):
     return float(xmax) * max(1.0, (e / (np.sqrt(np.pi) / 2)) ** 0.5)
 
 
-def assert_close(dt, got, ref, what="", scale=1.0):
-    """scale: see gain(); the bounds hold for max|x| = 1 and unit-energy taps."""
+def tol_for(dt, workload=None):
+    """(rel-L2, max-abs) bound of a path; FP8 has per-workload bounds."""
+    if dt == "fp8" and workload is not None:
+        return TOL_FP8_WORKLOAD[workload]
+    return TOL[dt]
+
+
+def assert_close(dt, got, ref, what="", scale=1.0, workload=None):
+    """scale: see gain(); the bounds hold for max|x| = 1 and unit-energy taps.
+    workload: a key of TOL_FP8_WORKLOAD for the measured workloads."""
     rel, mab = errors(got, ref)
-    r_tol, a_tol = TOL[dt]
+    r_tol, a_tol = tol_for(dt, workload)
     print("%s %-6s rel-L2 %.3e (tol %.1e)  max-abs %.3e (tol %.1e)" % (what, dt, rel, r_tol, mab, a_tol * scale))
     assert rel <= r_tol, "%s %s rel-L2 %.3e > %.1e" % (what, dt, rel, r_tol)
     assert mab <= a_tol * scale, "%s %s max-abs %.3e > %.1e" % (what, dt, mab, a_tol * scale)

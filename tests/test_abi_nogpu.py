@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     names = declared()
     for n in ("cwt_plan_create", "cwt_plan_destroy", "cwt_execute", "cwt_execute_batch",
               "cwt_num_frames", "cwt_status_string", "cwt_last_error", "cwt_plan_set_output",
-              "cwt_scale_frequencies", "cwt_batch_create", "cwt_batch_execute", "cwt_autotune"):
+              "cwt_scale_frequencies", "cwt_batch_create", "cwt_batch_execute", "cwt_autotune",
+              "cwt_autotune_batch"):
         assert n in names
 
 

@@ -131,10 +131,11 @@ def test_one_second_clip_32_scales(torch, cw, dt, hop):
     plan = cw.Plan(16000.0, np.arange(1, 33), hop, dt, signed=True)
     got = gpu_run(torch, plan, x)
     assert got.shape == ref.shape
-    assert_close(dt, got, ref, "1s/32sc hop=%d" % hop)
+    assert_close(dt, got, ref, "1s/32sc hop=%d" % hop, workload="1s32")
 
 
-C2_CASES = [(hop, snr) for hop in (1, 512) for snr in (-6.0, 0.0, 6.0)] + [(32, 0.0), (256, 0.0)]
+C2_CASES = ([(hop, snr) for hop in (1, 512) for snr in (-6.0, 0.0, 6.0)]
+            + [(32, 0.0), (128, 0.0), (256, 0.0), (1024, 0.0)])
 
 
 @pytest.mark.parametrize("dt", DTYPES)
@@ -147,7 +148,66 @@ def test_ten_second_clip_128_scales(torch, cw, dt, hop, snr):
     plan = cw.Plan(16000.0, np.arange(1, 129), hop, dt, signed=True)
     got = gpu_run(torch, plan, x)
     assert got.shape == ref.shape == (128, -(-160000 // hop))
-    assert_close(dt, got, ref, "10s/128sc hop=%d snr=%g" % (hop, snr))
+    assert_close(dt, got, ref, "10s/128sc hop=%d snr=%g" % (hop, snr), workload="10s128")
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("hop", [1, 128, 512])
+def test_ten_second_clip_magnitude_output(torch, cw, dt, hop):
+    """The default output, the scalogram |W| (Sec. II-A: the image is the
+    magnitude of the coefficients), against |oracle| on the 10 s / 128-scale
+    clip; ||a| - |b|| <= |a - b|, so the signed bounds hold."""
+    x = clip(2, 1, 160000, 0.0)
+    ref = np.abs(oracle_full(2, 1, 160000, 0.0, 128, hop))
+    plan = cw.Plan(16000.0, np.arange(1, 129), hop, dt)
+    got = gpu_run(torch, plan, x)
+    assert got.shape == ref.shape and got.min() >= 0.0
+    assert_close(dt, got, ref, "10s/128sc |W| hop=%d" % hop, workload="10s128")
+
+
+@pytest.mark.parametrize("hop", [1, 64])
+def test_constant_input_dc_leakage(torch, cw, hop):
+    """A constant input: away from the edges W = sum_m t[m], the wavelet's DC
+    leakage, sqrt(2 pi s) exp(-12.5) (1.87e-5 at s = 4), a sum of taps up to
+    ~0.4 that cancels to 1e-5 of their size.  BF16 operands carry 2^-9 of each
+    tap and lose the value entirely; the hi+lo split keeps ~2^-17 and stays
+    within its stated bound, as does FP32."""
+    n = 24000
+    x = np.ones(n, dtype=np.float32)
+    scales = [4.0, 16.0, 64.0, 128.0]
+    ref = oracle.cwt(x.astype(np.float64), scales, hop)
+    K = ref.shape[1]
+    k = np.arange(K) * hop
+    inner = (k >= 1100) & (k < n - 1100)
+    dc = np.array([math.sqrt(2 * math.pi * s) * math.exp(-12.5) for s in scales])
+    np.testing.assert_allclose(ref[:, inner], np.repeat(dc[:, None], inner.sum(), 1), rtol=1e-6)
+    err = {}
+    for dt in ("fp32", "bf16x3", "bf16"):
+        got = gpu_run(torch, cw.Plan(16000.0, scales, hop, dt, signed=True), x)
+        # rel-L2 means nothing on a near-zero W: the max-abs bound (stated for
+        # max|x| = 1) is the test
+        mab = float(np.abs(got - ref).max())
+        err[dt] = float(np.abs(got[:, inner] - ref[:, inner]).max())
+        print("constant input hop=%d %-6s max-abs %.3e (tol %.1e), interior %.3e (DC %.3e .. %.3e)" % (
+            hop, dt, mab, TOL[dt][1], err[dt], dc.min(), dc.max()))
+        assert mab <= TOL[dt][1]
+    # BF16 loses the DC value; the split products keep it
+    assert err["bf16x3"] < dc.max() < err["bf16"]
+    assert err["fp32"] < dc.min()
+
+
+@pytest.mark.parametrize("hop", [1, 64, 512])
+def test_fp8_faint_signal(torch, cw, hop):
+    """A clip peak-normalised to 1e-37: 448 / max|x| exceeds 2^128, so the FP8
+    signal scale is capped at 2^126 (the samples then reach 8.5, not 448).
+    Results stay finite and, divided by 1e-37, meet the FP8 bound against the
+    oracle of the same input."""
+    x = (clip(1, 0, 16000, 0.0).astype(np.float64) * 1e-37).astype(np.float32)
+    scales = np.arange(1, 33, dtype=np.float64)
+    ref = oracle.cwt(x.astype(np.float64), scales, hop) * 1e37
+    got = gpu_run(torch, cw.Plan(16000.0, scales, hop, "fp8", signed=True), x).astype(np.float64) * 1e37
+    assert np.isfinite(got).all()
+    assert_close("fp8", got, ref, "fp8 faint clip hop=%d" % hop)
 
 
 @pytest.mark.parametrize("dt", ["bf16", "fp8"])
@@ -168,7 +228,7 @@ def test_sixty_second_48k_geometric_sampled(torch, cw, dt, hop):
     ii[:8] = [0, 255, 255, 255, 128, 0, 255, 200]
     kk[:8] = [0, 0, K - 1, 1, K - 1, K - 1, K // 2, 3]
     ref = oracle.points(x.astype(np.float64), scales, hop, ii, kk)
-    assert_close(dt, got[ii, kk], ref, "60s/48k/256geo hop=%d (3000 samples)" % hop)
+    assert_close(dt, got[ii, kk], ref, "60s/48k/256geo hop=%d (3000 samples)" % hop, workload="60s256")
 
 
 # ---------------------------------------------------------------------------
@@ -414,6 +474,71 @@ def test_batch_against_oracle(torch, cw):
         assert_close("bf16", o.cpu().numpy(), ref, "batch hop=%d" % h)
 
 
+def _sampled_check(dt, got, x, scales, hop, rng, count, what, magnitude):
+    """got (host array [S][K]) against the oracle on `count` sampled
+    coefficients (first and last frames always included)."""
+    S, K = got.shape
+    ii = rng.integers(0, S, count)
+    kk = rng.integers(0, K, count)
+    ii[:4] = [0, S - 1, 0, S - 1]
+    kk[:4] = [0, 0, K - 1, K - 1]
+    ref = oracle.points(np.asarray(x, dtype=np.float64), scales, hop, ii, kk)
+    if magnitude:
+        ref = np.abs(ref)
+    return assert_close(dt, got[ii, kk], ref, what)
+
+
+def test_batch_of_256_uneven_clips_mixed_hops_graph_replays(torch, cw):
+    """The batching workload at its own shape: 256 clips, lengths uniform in
+    [1 s, 10 s] at 16 kHz, SNR uniform in [-6, 6] dB, hop per clip from
+    {64, 256, 512}, 128 scales, BF16, |W|, tile configuration tuned on the
+    batch itself, one persistent launch replayed from a captured HIP graph.  Every clip is checked against the FP64 oracle on
+    2,000 sampled coefficients and four clips in full; the graph is replayed
+    three times with other device work in between, each replay compared bit
+    for bit with the first and with a direct launch."""
+    n = 256
+    lens = synth.batch_lengths(synth.clip_seed(3, 0), n)
+    rng = np.random.default_rng(synth.clip_seed(3, 1))
+    snr = rng.uniform(-6.0, 6.0, n)
+    hops = rng.choice([64, 256, 512], n)
+    xs_h = [synth.make_clip(synth.clip_seed(3, 10 + i), int(lens[i]), 16000.0, float(snr[i])) for i in range(n)]
+    xs = [torch.from_numpy(x).cuda() for x in xs_h]
+    scales = np.arange(1, 129, dtype=np.float64)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (64, 256, 512)}
+    pl = [plans[int(h)] for h in hops]
+    B = cw.Batch(n)
+    untuned = [o.clone() for o in B(pl, xs, graph=False)]
+    chosen = cw.autotune_batch(pl, lens)               # the batch's own tile configuration
+    print("256-clip batch: tuned configuration %d" % chosen)
+    prep = B.prepare(pl, xs)
+    first = [o.clone() for o in prep.run(graph=True)]
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert torch.equal(untuned[i], first[i]), i
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda") * 2.0      # eager work between replays
+        for o in prep.outs:
+            o.fill_(-1.0)
+        outs = prep.run(graph=True)
+        torch.cuda.synchronize()
+        assert float(junk.abs().sum()) > 0
+        for i in range(n):
+            assert torch.equal(outs[i], first[i]), (rep, i)
+    direct = B(pl, xs, graph=False)
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert torch.equal(direct[i], first[i]), i
+    got = [o.cpu().numpy() for o in first]
+    full = {0, n - 1, int(np.argmax(lens)), int(np.argmin(lens))}
+    for i in range(n):
+        h = int(hops[i])
+        if i in full:
+            ref = np.abs(oracle.cwt(xs_h[i].astype(np.float64), scales, h))
+            assert_close("bf16", got[i], ref, "256-clip batch clip %d (len %d, hop %d, full)" % (i, lens[i], h))
+        _sampled_check("bf16", got[i], xs_h[i], scales, h, rng, 2000,
+                       "256-clip batch clip %d (len %d, hop %d, 2000 samples)" % (i, lens[i], h), True)
+
+
 def test_batch_rejects_mixed_plans(torch, cw):
     a = cw.Plan(16000.0, [1.0, 2.0], 4, "bf16")
     b = cw.Plan(16000.0, [1.0, 3.0], 4, "bf16")
@@ -491,7 +616,35 @@ def test_frequencies_and_autotune(torch, cw):
     x = torch.from_numpy(clip(1, 0, 16000, 0.0)).cuda()
     before = p(x)
     c = p.autotune(16000)
-    assert 0 <= c < p.num_configs and p.config == c
+    # the plan stays automatic; its launches of this class run the tuned choice
+    assert 0 <= c < p.num_configs and c == p.launch_config(16000, 1)
     after = p(x)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
+    # a set configuration is never overridden by a tuned one
+    q = cw.Plan(16000.0, [1.0, 5.0, 100.0], 32, "bf16")
+    q.set_config(5)
+    assert q.launch_config(16000, 1) == 5
+
+
+def test_autotune_batch_keys_on_length_and_clip_count(torch, cw):
+    """Tuning a batch records its choice for its own class only: the one-clip
+    launch of another length keeps the per-launch choice, and the tuned batch
+    gives the same bits as before tuning."""
+    scales = np.arange(1, 65)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (64, 256)}
+    p1 = cw.Plan(16000.0, scales, 64, "bf16")
+    single_before = p1.launch_config(100000, 1)
+    lens = [20000 + 1000 * i for i in range(40)]
+    pl = [plans[64 if i % 2 else 256] for i in range(40)]
+    xs = [torch.from_numpy(synth.make_clip(700 + i, n, 16000.0, 0.0)).cuda() for i, n in enumerate(lens)]
+    before = cw.execute_batch(pl, xs)
+    c = cw.autotune_batch(pl, lens)
+    assert 0 <= c < plans[64].num_configs
+    after = cw.execute_batch(pl, xs)
+    torch.cuda.synchronize()
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
+    assert p1.launch_config(100000, 1) == single_before
+    with pytest.raises(cw.CwtError):
+        cw.autotune_batch([plans[64], cw.Plan(16000.0, scales, 64, "fp16")], [1000, 1000])

@@ -1,10 +1,12 @@
 """Serving on the GPU: requests admitted while others run, overlapping
-batches on several streams, and every result bit-identical to the same request
-run alone (the summation order does not depend on the batch)."""
+batches on several streams, every result bit-identical to the same request
+run alone (the summation order does not depend on the batch) and within the
+BF16 bound of the FP64 oracle."""
 import numpy as np
 import pytest
 
-from gpu_util import torch_cuda
+import oracle
+from gpu_util import TOL, assert_close, errors, torch_cuda
 from paper_2408_14302_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -26,6 +28,31 @@ def test_results_same_alone_and_in_the_mix():
         alone = p(x)
         torch.cuda.synchronize()
         assert torch.equal(alone, r.output), r.rid
+    # and every served result against the FP64 oracle: |W| on 300 sampled
+    # coefficients per request, two requests in full
+    rng = np.random.default_rng(5)
+    host = {}
+    full = {reqs[0].rid, reqs[len(reqs) // 2].rid}
+    worst = 0.0
+    for r in reqs:
+        x, p = r.payload
+        key = id(x)
+        if key not in host:
+            host[key] = x.cpu().numpy().astype(np.float64)
+        xh = host[key]
+        got = r.output.cpu().numpy()
+        S, K = got.shape
+        if r.rid in full:
+            ref = np.abs(oracle.cwt(xh, p.scales, p.hop))
+            assert_close("bf16", got, ref, "served request %d (S %d, hop %d, full)" % (r.rid, S, p.hop))
+        ii = rng.integers(0, S, 300)
+        kk = rng.integers(0, K, 300)
+        kk[:2] = [0, K - 1]
+        ref = np.abs(oracle.points(xh, p.scales, p.hop, ii, kk))
+        rel, mab = errors(got[ii, kk], ref)
+        worst = max(worst, mab)
+        assert rel <= TOL["bf16"][0] and mab <= TOL["bf16"][1], (r.rid, S, p.hop, rel, mab)
+    print("served results against the oracle: worst sampled max-abs %.3e over %d requests" % (worst, len(reqs)))
 
 
 def test_budget_and_rejection_on_gpu():

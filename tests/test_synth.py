@@ -18,9 +18,42 @@ def test_peak_normalised():
         assert abs(float(np.abs(x).max()) - 1.0) < 1e-6
 
 
-def test_snr_achieved():
+def test_clip_is_the_normalised_mix_of_its_parts():
     for snr in (-6.0, 0.0, 6.0, 3.3):
-        assert abs(synth.achieved_snr_db(31, 160000, 16000.0, snr) - snr) < 0.01
+        tone, noise = synth.clip_parts(31, 160000, 16000.0, snr)
+        x = synth.make_clip(31, 160000, 16000.0, snr)
+        mix = tone + noise
+        np.testing.assert_array_equal(x, (mix / np.abs(mix).max()).astype(np.float32))
+        # the mixing SNR, measured on the parts (mean-square ratio)
+        assert abs(10 * np.log10(np.mean(tone ** 2) / np.mean(noise ** 2)) - snr) < 1e-9
+
+
+def test_tone_is_harmonic_and_noise_is_pink():
+    fs, n = 16000.0, 160000
+    for seed in (5, 31, 77):
+        f0, nh = synth.clip_params(seed)
+        tone, noise = synth.clip_parts(seed, n, fs, 0.0)
+        # Hann-windowed spectrum: a sinusoid of amplitude a puts energy
+        # n a^2 sum(w^2) / 4 into the bins within a few of its frequency
+        w = np.hanning(n)
+        P = np.abs(np.fft.rfft(tone * w)) ** 2
+        f = np.fft.rfftfreq(n, 1.0 / fs)
+        e1 = n * float(np.sum(w * w)) / 4.0
+        for k in range(1, nh + 1):
+            if k * f0 >= fs / 2:
+                break
+            band = np.abs(f - k * f0) <= 0.5
+            amp = float(np.sqrt(P[band].sum() / e1))
+            assert abs(amp - 1.0 / k) < 1e-3 / k, (seed, k, amp)
+        off = np.ones_like(f, dtype=bool)
+        for k in range(1, nh + 1):
+            off &= np.abs(f - k * f0) > 0.5
+        assert P[off].sum() < 1e-4 * P.sum()
+        # pink: equal power per octave (power density ~ 1/f), within 20% over
+        # the octaves from 20 Hz to 5.12 kHz
+        p = np.abs(np.fft.rfft(noise)) ** 2
+        octs = [float(p[(f >= lo) & (f < 2 * lo)].sum()) for lo in 20.0 * 2.0 ** np.arange(8)]
+        assert max(octs) / min(octs) < 1.2, octs
 
 
 def test_tone_parameters_in_range():

@@ -107,3 +107,48 @@ def test_image_identity_size_constant_and_floor():
     z[1, 2] = 1.0                                   # one sample above the floor
     img = T.scalogram_image(z, 1e-3, 3, 4)          # floor -60 dB, peak 0 dB
     assert img[1, 2] == 1.0 and img.sum() == 1.0
+
+
+def test_image_min_max_come_from_the_full_resolution_scalogram():
+    # A 4 x 8 scalogram at -40 dB with one 0 dB coefficient, halved in both
+    # directions: every output pixel averages a 2 x 2 block with weights 1/4,
+    # so the spike shows at -30 dB.  Normalised over the full-resolution D
+    # (-40 .. 0 dB) that pixel is 0.25 and no pixel reaches 1; normalised over
+    # the resized image it would be 1.
+    w = np.full((4, 8), 0.01)
+    w[1, 3] = 1.0
+    img = T.scalogram_image(w, 1e-6, 2, 4)
+    assert img.shape == (2, 4)
+    np.testing.assert_allclose(img[0, 1], 0.25, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(img.max(), 0.25, rtol=0, atol=1e-14)
+    assert img.min() == 0.0
+    # and the mirror case: a dip averaged away leaves the image minimum above 0
+    w = np.full((4, 8), 1.0)
+    w[2, 5] = 0.01
+    img = T.scalogram_image(w, 1e-6, 2, 4)
+    np.testing.assert_allclose(img[1, 2], 0.75, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(img.min(), 0.75, rtol=0, atol=1e-14)
+    assert img.max() == 1.0
+
+
+def test_decimated_cwt_reaches_the_hop_strided_transform_for_a_slow_signal():
+    # Independent of the route's own code: for a signal whose spectrum lies far
+    # below the decimated Nyquist rate, decimating by H and transforming at
+    # scales s/H gives the hop-H transform divided by sqrt(H): both sums are
+    # Riemann sums of the same integral (spacing H against 1, hence a factor
+    # H), and the coarse taps carry 1/sqrt(s/H) instead of 1/sqrt(s).  For a
+    # smooth, band-limited integrand the two agree to rounding at frames whose
+    # support stays inside the clip; at the edges the zero padding is a jump
+    # that the two spacings sample differently.
+    n, H = 4096, 4
+    t = np.arange(n)
+    x = np.cos(2 * np.pi * t / 512.0) + 0.5 * np.sin(2 * np.pi * t / 300.0 + 0.3)
+    scales = np.array([32.0, 48.0, 64.0])
+    got = T.decimated_cwt(x, scales, H) * np.sqrt(H)
+    ref = oracle.cwt(x, scales, H)
+    k = np.arange(ref.shape[1])
+    for i, s in enumerate(scales):
+        M = int(8 * s)
+        inner = (k * H - M >= 0) & (k * H + M < n)
+        assert inner.sum() > 500
+        np.testing.assert_allclose(got[i, inner], ref[i, inner], rtol=0, atol=1e-12)
