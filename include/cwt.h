@@ -126,6 +126,23 @@ cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs,
                              void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * contract and results as cwt_execute_batch, bit for bit, but the call
+ * allocates nothing.  The batch descriptors go to a fixed device array of
+ * 36 KiB per GPU, held until the process ends, written by small kernels on
+ * `stream` that carry them in their arguments; no hipMalloc, hipFree, host
+ * staging buffer or copy.  At most 512 clips per call (CWT_ERR_INVALID_ARG
+ * beyond).  Every call on one GPU shares that array: calls whose work
+ * overlaps on the device (on different streams, or from several threads)
+ * race and must be ordered by the caller; calls queued on one stream are
+ * ordered by it.  The plans' device must be the current device.
+ */
+cwt_status cwt_execute_batch_noalloc(const cwt_plan_t* plans, const float* const* xs,
+                                     const int64_t* lens, float* const* outs, int32_t n,
+                                     void* stream);
+
+/*
  * Explicit batch context: owns two pinned and two device descriptor buffers
  * sized for up to max_clips clips and captured HIP graphs (descriptor upload +
  * the persistent launch, or the launch alone) that cwt_batch_execute replays.

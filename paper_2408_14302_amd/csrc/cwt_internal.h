@@ -159,4 +159,16 @@ hipError_t decode_bank_taps(int dt, const uint8_t* d_frags, const MfmaBlock* d_b
                             const float* d_direct, const DirectGroup* d_dgroups,
                             int sorted_pos, int M, double* d_out, hipStream_t st);
 
+// Allocation-free batches (noalloc.hip): descriptors of up to
+// kNoallocMaxClips clips in a file-scope device array of kNoallocScratchBytes
+// per GPU, written by kernels that carry them in their arguments
+// (kDescPieceWords 16-byte words, under 4 KiB of arguments, per launch).
+constexpr int kNoallocMaxClips = 512;
+constexpr int kNoallocScratchBytes = 36 * 1024;   // >= 16 + 512 * 64 + 4 * 513 + 16
+constexpr int kDescPieceWords = 240;
+// The device address of that GPU's array (looked up once, `device` current).
+hipError_t scratch_address(int device, void** out);
+// Write `bytes` of host descriptors to device memory dst, in order on stream s.
+hipError_t put_desc(const uint8_t* host, size_t bytes, uint8_t* dst, hipStream_t s);
+
 }  // namespace cwth

@@ -1413,6 +1413,42 @@ cwt_status cwt_execute_batch(const cwt_plan_t* plans, const float* const* xs, co
     }
 }
 
+cwt_status cwt_execute_batch_noalloc(const cwt_plan_t* plans, const float* const* xs, const int64_t* lens,
+                                     float* const* outs, int32_t n, void* stream) {
+    static_assert(16 + sizeof(ClipArg) * kNoallocMaxClips + sizeof(int32_t) * (kNoallocMaxClips + 1) <=
+                      (size_t)kNoallocScratchBytes, "scratch too small for the clip maximum");
+    try {
+        if (n < 0) return fail(CWT_ERR_INVALID_ARG, "n < 0");
+        if (n == 0) return CWT_OK;
+        if (n > kNoallocMaxClips)
+            return fail(CWT_ERR_INVALID_ARG, "cwt_execute_batch_noalloc takes at most 512 clips per call");
+        cwt_status st = batch_validate(plans, xs, lens, outs, n);
+        if (st != CWT_OK) return st;
+        const cwt_plan_s* p0 = plans[0];
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess) return fail(CWT_ERR_DEVICE, "hipGetDevice failed");
+        if (p0->device != dev) return fail(CWT_ERR_INVALID_ARG, "plans belong to another device than the current one");
+        void* sp = nullptr;
+        HIP_TRY(scratch_address(dev, &sp), "descriptor scratch address");
+        // host working storage on the stack: nothing is allocated
+        int order[kNoallocMaxClips];
+        ClipArg clips[kNoallocMaxClips];
+        int64_t ctiles[kNoallocMaxClips];
+        alignas(16) uint8_t host[kNoallocScratchBytes];
+        BatchLaunch bl;
+        st = batch_prepare(plans, xs, lens, outs, n, p0->cus, -1, BatchScratch{order, clips, ctiles}, host,
+                           sizeof(host), &bl);
+        if (st != CWT_OK || bl.nc == 0) return st;
+        uint8_t* dd = (uint8_t*)sp;
+        HIP_TRY(put_desc(host, bl.used_bytes, dd, (hipStream_t)stream), "descriptor write");
+        batch_bind(&bl, dd);
+        HIP_TRY(batch_launch(bl, dd, (hipStream_t)stream), bl.fp32 ? "direct batch launch" : "persistent launch");
+        return CWT_OK;
+    } catch (...) {
+        return fail(CWT_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
 int32_t cwt_plan_config(cwt_plan_t plan) { return plan ? plan->cfg : -1; }
 
 int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips) {

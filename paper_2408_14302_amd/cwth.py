@@ -34,6 +34,7 @@ _SIGS = {
     "cwt_scale_frequencies": (_i32, [_c_plan, _vp]),
     "cwt_execute": (_i32, [_c_plan, _vp, _i64, _vp, _vp]),
     "cwt_execute_batch": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "cwt_execute_batch_noalloc": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp]),
     "cwt_batch_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
     "cwt_batch_destroy": (_i32, [_vp]),
     "cwt_batch_execute": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp]),
@@ -286,6 +287,16 @@ def execute_batch(plans, xs, outs=None, stream=None):
         outs = _outs_for(plans, xs, stream)
     n, P, X, L, O = _arrays(plans, xs, outs)
     _check(_lib.cwt_execute_batch(P, X, L, O, n, _stream_ptr(stream)), "cwt_execute_batch")
+    return outs
+
+
+def execute_batch_noalloc(plans, xs, outs, stream=None):
+    """cwt_execute_batch_noalloc: one persistent launch that allocates no
+    device memory (caller-owned outputs; at most 512 clips)."""
+    for x in xs:
+        _check_signal(x)
+    n, P, X, L, O = _arrays(plans, xs, outs)
+    _check(_lib.cwt_execute_batch_noalloc(P, X, L, O, n, _stream_ptr(stream)), "cwt_execute_batch_noalloc")
     return outs
 
 
