@@ -206,6 +206,16 @@ int32_t cwt_plan_config(cwt_plan_t plan);
  * Returns -1 for a NULL plan, len < 1 or n_clips < 1. */
 int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips);
 int32_t cwt_plan_num_configs(cwt_plan_t plan);
+
+/* The kind of configuration `index` for this plan: 0 = tiles of 32-scale
+ * blocks (every hop), 1 = Toeplitz tiles (hop 1, BF16/FP16: each scale runs
+ * its own K range; the default there), -1 = no such configuration.  BF16,
+ * FP16 and BF16x3 results are bit-identical across the configurations of one
+ * kind (and between a clip alone and in a batch); the two kinds sum each
+ * coefficient's products in different groups of 16 and agree within the
+ * dtype's tolerance.  A batch runs a Toeplitz plan's clips as Toeplitz tiles
+ * (configuration 14). */
+int32_t cwt_plan_config_kind(cwt_plan_t plan, int32_t index);
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
 
 /*

@@ -140,6 +140,43 @@ __global__ void k_gen_mfma(const double* __restrict__ scales, int nscales,
     }
 }
 
+// Toeplitz bank: one thread per (group, step, scale, lane); the lane's
+// eight taps t[jb + 16 d + 8 (lane / 32) + e - lane % 32], e = 0 .. 7.
+template <int DT>
+__global__ void k_gen_toep(const double* __restrict__ scales, int nscales, const ToepGroup* __restrict__ groups,
+                           int ngroups, uint8_t* __restrict__ frags) {
+    const int g = blockIdx.y;
+    if (g >= ngroups) return;
+    const ToepGroup G = groups[g];
+    const int total = G.D * kToepScales * 64;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int lane = i % 64, sc = (i / 64) % kToepScales, d = i / (64 * kToepScales);
+        const int pos = g * kToepScales + sc;
+        const bool valid = pos < nscales;
+        const double s = valid ? scales[pos] : 1.0;
+        const int M = valid ? (int)floor(8.0 * s) : -1;
+        uint16_t* dst = (uint16_t*)(frags + G.frag_off + (int64_t)i * 16);
+        const int m0 = G.jb + 16 * d + 8 * (lane / 32) - lane % 32;
+        for (int e = 0; e < 8; ++e) {
+            const int m = m0 + e;
+            const double t = (m >= -M && m <= M) ? morlet_tap(s, m) : 0.0;
+            dst[e] = DT == DT_BF16 ? to_bf16_bits(t) : to_f16_bits(t);
+        }
+    }
+}
+
+hipError_t gen_toep_bank(int dt, const double* d_scales_sorted, int nscales, const ToepGroup* d_groups,
+                         int ngroups, uint8_t* d_frags, hipStream_t st) {
+    dim3 grid(64, ngroups), block(256);
+    if (dt == DT_BF16)
+        hipLaunchKernelGGL((k_gen_toep<DT_BF16>), grid, block, 0, st, d_scales_sorted, nscales, d_groups, ngroups, d_frags);
+    else if (dt == DT_FP16)
+        hipLaunchKernelGGL((k_gen_toep<DT_FP16>), grid, block, 0, st, d_scales_sorted, nscales, d_groups, ngroups, d_frags);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t gen_direct_bank(const double* d_scales_sorted, int nscales, const DirectGroup* d_groups,
                            int ngroups, float* d_taps, int64_t, hipStream_t st) {
     dim3 grid(16, ngroups), block(256);

@@ -54,6 +54,26 @@ struct MfmaBlock {
     float inv_alpha[kBlockRows]; // FP8 only: 1/alpha_r; 1 otherwise
 };
 
+// Toeplitz bank (BF16/FP16, hop 1): groups of kToepScales consecutive sorted
+// scales.  Group g runs K-steps d = 0 .. D-1 over p = jb + 16 d + u (u < 16)
+// and stores, for every step and scale, one B-operand fragment in lane order:
+// lane l holds t[jb + 16 d + 8 (l / 32) + e - l % 32], e = 0 .. 7 (zero outside
+// the scale's support), 1 KiB per fragment, the group's scales interleaved
+// per step.
+constexpr int kToepScales = 2;
+constexpr int kToepBatchNB = 2;    // 1024-frame blocks per wave in batch tiles
+// First p and K-steps of a group whose widest scale has half-width M, and the
+// LDS window (2-byte operands) of a tile of 4 * 1024 * NB frames over D steps.
+__host__ __device__ constexpr int toep_jb(int M) { return -8 * ((M + 7) / 8); }
+__host__ __device__ constexpr int toep_steps(int M) { return (((M + 32 - toep_jb(M) + 15) / 16) + 3) & ~3; }
+__host__ __device__ constexpr int toep_window_bytes(int NB, int D) { return (kMfmaWaves * 1024 * NB + 16 * D) * 2; }
+struct ToepGroup {
+    int32_t jb;            // first p of step 0: a multiple of 8, <= -M of every scale
+    int32_t D;             // K-steps (a multiple of 4); jb + 16 D >= M + 32
+    int32_t rows[kToepScales];   // caller rows (-1: none)
+    int64_t frag_off;      // byte offset of step 0 in the Toeplitz fragments
+};
+
 // ---------------------------------------------------------------------------
 // Per-launch arguments.
 
@@ -75,7 +95,8 @@ struct ClipArg {
 
 // LINEAR: chunked linear window, one block per tile; ROWS: chunked per-frame
 // rows (SPLIT tiles); WIN: the whole linear window of a tile staged once.
-enum StageMode : int { STAGE_LINEAR = 0, STAGE_ROWS = 1, STAGE_WIN = 2 };
+// TOEP: hop-1 Toeplitz tiles (one scale group over 4 * 1024 * NB frames).
+enum StageMode : int { STAGE_LINEAR = 0, STAGE_ROWS = 1, STAGE_WIN = 2, STAGE_TOEP = 3 };
 
 struct MfmaArgs {
     const uint8_t* frags;
@@ -90,6 +111,10 @@ struct MfmaArgs {
     int32_t split_wb;      // row-layout tiles: scale blocks per work-group (1, 2 or 4)
     int32_t split_chunk;   // row-layout tiles: K-steps per chunk (a multiple of 8)
     int32_t shm_bytes;     // dynamic LDS of the launch (the largest need over its clips)
+    // Toeplitz tiles (STAGE_TOEP clips)
+    const uint8_t* tfrags;
+    const ToepGroup* tgroups;
+    int32_t ntgroups;
     // single clip (grid launch)
     ClipArg clip;
     // batch (persistent launch)
@@ -119,6 +144,10 @@ hipError_t launch_direct_batch(const DirectArgs& a, const ClipArg* d_clips, cons
 hipError_t launch_mfma(int dt, int cfgA, int nb, const MfmaArgs& a, int persistent,
                        int grid, hipStream_t s);
 int mfma_max_lds_bytes();
+// Toeplitz tiles of one clip (a.clip, mode STAGE_TOEP): NB = 1, 2 or 4
+// 1024-frame blocks per wave, grid = a.ntgroups * a.clip.ntile.
+hipError_t launch_toep(int dt, int NB, const MfmaArgs& a, int grid, hipStream_t s);
+int toep_occupancy(int dt, int NB, size_t shm);
 // Allow every MFMA kernel the full dynamic LDS; call once, outside graph capture.
 hipError_t mfma_init_attributes();
 // Resident work-groups per CU for a kernel instance with `shm` bytes of dynamic LDS.
@@ -155,6 +184,8 @@ hipError_t gen_direct_bank(const double* d_scales_sorted, int nscales, const Dir
 hipError_t gen_mfma_bank(int dt, const double* d_scales_sorted, int nscales,
                          const MfmaBlock* d_blocks, int nblocks, uint8_t* d_frags,
                          int64_t total_bytes, const double* d_alpha, hipStream_t st);
+hipError_t gen_toep_bank(int dt, const double* d_scales_sorted, int nscales, const ToepGroup* d_groups,
+                         int ngroups, uint8_t* d_frags, hipStream_t st);
 hipError_t decode_bank_taps(int dt, const uint8_t* d_frags, const MfmaBlock* d_blocks,
                             const float* d_direct, const DirectGroup* d_dgroups,
                             int sorted_pos, int M, double* d_out, hipStream_t st);

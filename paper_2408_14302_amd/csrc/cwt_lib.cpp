@@ -93,10 +93,11 @@ static cwt_status current_device(int* dev, DeviceInfo* info) {
 // frames; chunk = upper bound of the K-steps per LDS buffer of chunked LINEAR
 // tiles (a multiple of 8; pick_chunk() shrinks it to what the LDS budget holds).
 struct MfmaCfg {
-    int A;
+    int A;       // Toeplitz configurations: 1024-frame blocks per wave (NB)
     int wb;
     int ws;
     int chunk;
+    int toep;    // 1: hop-1 Toeplitz tiles (BF16/FP16), 4 * 1024 * A frames per work-group
 };
 static const MfmaCfg kMfmaCfgs[] = {
     {4, 4, 1, 32},   // 0: 512 frames, every wave runs all 4 blocks
@@ -112,7 +113,11 @@ static const MfmaCfg kMfmaCfgs[] = {
     {8, 4, 4, 32},   // 10: 256 frames, one block per wave (WIN only, BF16/FP16)
     {8, 4, 2, 32},   // 11: 512 frames, blocks {0,3} / {1,2} per wave (WIN only, BF16/FP16)
     {8, 4, 1, 32},   // 12: 1024 frames, every wave runs all 4 blocks (WIN only, BF16/FP16)
+    {4, 0, 0, 0, 1}, // 13: Toeplitz, 16384 frames x one scale pair per work-group (hop 1, BF16/FP16)
+    {2, 0, 0, 0, 1}, // 14: Toeplitz, 8192 frames
+    {1, 0, 0, 0, 1}, // 15: Toeplitz, 4096 frames
 };
+static const int kToepCfg0 = 13;   // the Toeplitz configurations are 13 .. 15
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 static const int kFp8Cfg = 5;   // FP8's fallback configuration (see cfg_fits)
 
@@ -266,8 +271,17 @@ struct Bank {
     int64_t frag_bytes = 0;
     int Mmax = 0;
     int win_steps[3] = {0, 0, 0};      // widest union K range of a group of 1, 2, 4 blocks
+    // Toeplitz fragments (BF16/FP16; built by the first hop-1 plan, ensure_toep)
+    std::mutex toep_mu;
+    bool toep_built = false;
+    std::vector<ToepGroup> tgroups;
+    ToepGroup* d_tgroups = nullptr;
+    uint8_t* d_tfrags = nullptr;
+    int toep_Dmax = 0;
 
     ~Bank() {
+        if (d_tgroups) (void)hipFree(d_tgroups);
+        if (d_tfrags) (void)hipFree(d_tfrags);
         if (d_dtaps) (void)hipFree(d_dtaps);
         if (d_dgroups) (void)hipFree(d_dgroups);
         if (d_frags) (void)hipFree(d_frags);
@@ -411,6 +425,53 @@ static cwt_status acquire_bank(int dt, int device, const std::vector<double>& sc
     return CWT_OK;
 }
 
+// Toeplitz windows must fit the WIN budget at one block per wave.
+static bool toep_fits(const Bank& bk, int NB) { return toep_window_bytes(NB, toep_steps(bk.Mmax)) <= kWinBudget; }
+
+// Build the bank's Toeplitz fragments once (BF16/FP16 banks whose widest
+// window fits): groups of kToepScales consecutive sorted scales, jb = -M of
+// the group rounded down to a multiple of 8, D = ceil((M + 32 - jb) / 16)
+// rounded up to a multiple of 4.
+static cwt_status ensure_toep(Bank& bk) {
+    std::lock_guard<std::mutex> lk(bk.toep_mu);
+    if (bk.toep_built) return CWT_OK;
+    if (bk.dt != DT_BF16 && bk.dt != DT_FP16) return fail(CWT_ERR_UNSUPPORTED, "Toeplitz tiles hold BF16/FP16 only");
+    const int S = (int)bk.scales.size();
+    const int ng = (S + kToepScales - 1) / kToepScales;
+    std::vector<ToepGroup> gs(ng);
+    int64_t off = 0;
+    int dmax = 0;
+    for (int g = 0; g < ng; ++g) {
+        ToepGroup& G = gs[g];
+        int Mg = 0;
+        for (int r = 0; r < kToepScales; ++r) {
+            const int p = g * kToepScales + r;
+            G.rows[r] = p < S ? bk.sorted_to_caller[p] : -1;
+            if (p < S) Mg = std::max(Mg, bk.M_sorted[p]);
+        }
+        G.jb = toep_jb(Mg);
+        G.D = toep_steps(Mg);
+        G.frag_off = off;
+        off += (int64_t)G.D * kToepScales * 1024;
+        dmax = std::max(dmax, G.D);
+    }
+    std::vector<double> sorted(S);
+    for (int p = 0; p < S; ++p) sorted[p] = bk.scales[bk.sorted_to_caller[p]];
+    double* d_sorted = nullptr;
+    HIP_TRY(hipMalloc(&d_sorted, sizeof(double) * S), "bank scales");
+    std::unique_ptr<double, void (*)(double*)> g1(d_sorted, [](double* q) { (void)hipFree(q); });
+    HIP_TRY(hipMemcpy(d_sorted, sorted.data(), sizeof(double) * S, hipMemcpyHostToDevice), "bank scales copy");
+    HIP_TRY(hipMalloc(&bk.d_tfrags, off), "Toeplitz bank");
+    HIP_TRY(hipMalloc(&bk.d_tgroups, sizeof(ToepGroup) * ng), "Toeplitz groups");
+    HIP_TRY(hipMemcpy(bk.d_tgroups, gs.data(), sizeof(ToepGroup) * ng, hipMemcpyHostToDevice), "Toeplitz groups copy");
+    HIP_TRY(gen_toep_bank(bk.dt, d_sorted, S, bk.d_tgroups, ng, bk.d_tfrags, 0), "Toeplitz bank generation");
+    HIP_TRY(hipDeviceSynchronize(), "Toeplitz bank generation");
+    bk.tgroups = std::move(gs);
+    bk.toep_Dmax = dmax;
+    bk.toep_built = true;
+    return CWT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Plans.
 // One clip's tile layout (see clip_layout()).
@@ -436,8 +497,9 @@ struct cwt_plan_s {
     ClipLayout lay;      // MFMA layout under cfg ...
     int lay_chunk = 8;   // ... for chunked LINEAR tiles of this chunk
     bool cfg_user = false;    // configuration set by cwt_plan_set_config: no tuned override
-    bool cfg_auto = false;    // default configuration: each launch picks 6, 4 or 5 (auto_cfg)
-    ClipLayout auto_lay[3];   // layouts under configurations 6, 4 and 5 for that choice
+    bool cfg_auto = false;    // default configuration: each launch picks one of auto_set (auto_cfg)
+    int auto_set[3] = {6, 4, 5};   // scale-block tiles 6, 4, 5, or Toeplitz tiles 13, 14, 15
+    ClipLayout auto_lay[3];   // layouts under those configurations
 };
 
 // ---------------------------------------------------------------------------
@@ -575,8 +637,13 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
 // 512 than with 32-frame tiles throughout (tap fragments shared by two frame
 // blocks), equal at 1024 and 4% slower at 384; single clips there have too
 // few frames for the wider tiles and keep 5.  With no whole window, 5.
+static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop);
+
 static int default_cfg(const cwt_plan_s* p, int hop) {
     if (p->dt == DT_FP32) return 0;
+    // hop 1 at 16-bit operands: Toeplitz tiles (each scale runs its own K
+    // range, ~1.03x the algorithmic work against ~1.30x for 32-scale blocks)
+    if (cfg_fits(p, kToepCfg0, hop)) return kToepCfg0;
     auto win = [&](int cfg) {
         const MfmaCfg& c = kMfmaCfgs[cfg];
         return clip_layout(p->dt, *p->bank, hop, c, c.chunk).s.mode == STAGE_WIN;
@@ -594,6 +661,10 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     if (p->dt == DT_FP32) return cfg == 0;
     if (cfg < 0 || cfg >= kNumMfmaCfgs) return false;
     const MfmaCfg& c = kMfmaCfgs[cfg];
+    // Toeplitz tiles: hop 1, 16-bit operands, a built Toeplitz bank whose
+    // widest window fits at this tile size
+    if (c.toep)
+        return hop == 1 && (p->dt == DT_BF16 || p->dt == DT_FP16) && p->bank->toep_built && toep_fits(*p->bank, c.A);
     // FP8 scales the signal per 128-frame segment up to hop 128 (fp8_beta):
     // every tile must lie in one segment, i.e. have at most 128 frames.
     // Configuration 5 (32-frame WIN, 128-frame chunked and 32-128-frame row
@@ -616,6 +687,23 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
 // depends only on (dtype, bank, hop, configuration), never on the batch.
 static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c, int chunk) {
     ClipLayout L;
+    if (c.toep) {
+        // Toeplitz tiles for hop-1 clips of a built bank; any other clip of a
+        // launch under a Toeplitz configuration takes configuration 6's tiles
+        if (hop == 1 && bk.toep_built && toep_fits(bk, c.A)) {
+            L.s.mode = STAGE_TOEP;
+            L.s.copies = 1;
+            L.s.swz = -1;
+            L.s.cso = 0;
+            L.s.bytes = toep_window_bytes(c.A, bk.toep_Dmax);
+            L.s.raw_bytes = 0;
+            L.F = kMfmaWaves * 1024 * c.A;
+            L.groups = (int64_t)bk.tgroups.size();
+            return L;
+        }
+        const MfmaCfg& h = kMfmaCfgs[6];
+        return clip_layout(dt, bk, hop, h, h.chunk);
+    }
     const int nblk = (int)bk.blocks.size(), cap = wb_cap(nblk);
     for (int wb = std::min(c.wb, cap); wb <= cap; wb *= 2) {
         const int ws = std::min(c.ws, wb);
@@ -651,7 +739,7 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
 // Dynamic LDS a layout needs: one window (WIN), two buffers plus the raw
 // window (LINEAR), two row buffers (ROWS).
 static int64_t layout_lds(const ClipLayout& L) {
-    if (L.s.mode == STAGE_WIN) return L.s.bytes;
+    if (L.s.mode == STAGE_WIN || L.s.mode == STAGE_TOEP) return L.s.bytes;
     return 2 * L.s.bytes + L.s.raw_bytes;
 }
 
@@ -661,9 +749,14 @@ static void set_cfg(cwt_plan_s* p, int cfg) {
     p->cfg_auto = false;
     if (p->dt == DT_FP32) return;
     const MfmaCfg& c = kMfmaCfgs[cfg];
-    p->lay_chunk = pick_chunk(p->dt, p->hop, 128 * c.A, c.chunk);
+    p->lay_chunk = c.toep ? 8 : pick_chunk(p->dt, p->hop, 128 * c.A, c.chunk);
     p->lay = clip_layout(p->dt, *p->bank, p->hop, c, p->lay_chunk);
 }
+
+// Toeplitz formulation (configurations 13 .. 15) of a plan; batches run its
+// clips as tiles of kToepBatchNB blocks per wave (configuration kToepBatchCfg).
+static bool plan_toep(const cwt_plan_s* p) { return p->dt != DT_FP32 && kMfmaCfgs[p->cfg].toep != 0; }
+static const int kToepBatchCfg = 14;   // kMfmaCfgs[14].A == kToepBatchNB
 
 // The default configuration (6) is chosen for throughput when work is
 // plentiful; a launch with few frames fills the chip better with smaller
@@ -677,11 +770,14 @@ static void set_cfg(cwt_plan_s* p, int cfg) {
 // in every case, where a fixed one is up to 2x slower.  BF16/FP16/BF16x3
 // results do not depend on the configuration.
 static const int kAutoCfgs[3] = {6, 4, 5};
+static const int kAutoToep[3] = {13, 14, 15};   // Toeplitz tiles of 16384, 8192, 4096 frames
 
 static void set_auto(cwt_plan_s* p) {
     p->cfg_auto = true;
+    const int* set = kMfmaCfgs[p->cfg].toep ? kAutoToep : kAutoCfgs;
     for (int i = 0; i < 3; ++i) {
-        const MfmaCfg& c = kMfmaCfgs[kAutoCfgs[i]];
+        p->auto_set[i] = set[i];
+        const MfmaCfg& c = kMfmaCfgs[set[i]];
         p->auto_lay[i] = clip_layout(p->dt, *p->bank, p->hop, c, c.chunk);
     }
 }
@@ -693,8 +789,8 @@ static int auto_cfg(const cwt_plan_s* p, WG&& wgs) {
     const int64_t need = 2 * (int64_t)std::max(1, p->cus);
     for (int i = 0; i < 3; ++i) {
         const ClipLayout& L = p->auto_lay[i];
-        if (L.s.mode != STAGE_WIN) continue;
-        if (i == 2 || wgs(L) >= need) return kAutoCfgs[i];
+        if (L.s.mode != STAGE_WIN && L.s.mode != STAGE_TOEP) continue;
+        if (i == 2 || wgs(L) >= need) return p->auto_set[i];
     }
     return p->cfg;
 }
@@ -730,7 +826,7 @@ static int with_tuned(const cwt_plan_t* plans, const int64_t* lens, int n, int c
     }
     if (cnt == 0) return cfg;
     const int t = tuned_lookup(launch_class(p0, hlo, hhi, cnt, sum / cnt));
-    if (t < 0) return cfg;
+    if (t < 0 || kMfmaCfgs[t].toep != kMfmaCfgs[cfg].toep) return cfg;   // never across formulations
     for (int i = 0; i < n; ++i)
         if (lens[i] > 0 && !cfg_fits(plans[i], t, plans[i]->hop)) return cfg;
     return t;
@@ -787,6 +883,21 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
         return CWT_OK;
     }
     const MfmaCfg& c = kMfmaCfgs[cfg];
+    if (c.toep) {
+        MfmaArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.signed_out = p->signed_out;
+        a.tfrags = bk.d_tfrags;
+        a.tgroups = bk.d_tgroups;
+        a.ntgroups = (int)bk.tgroups.size();
+        ClipLayout L;
+        a.clip = make_clip(p, x, len, out, c, cfg == p->cfg, 8, &L, &tiles);
+        if (L.s.mode != STAGE_TOEP) return fail(CWT_ERR_INTERNAL, "Toeplitz configuration without Toeplitz tiles");
+        a.shm_bytes = (int32_t)layout_lds(L);
+        if (tiles > 0x7fffffff) return fail(CWT_ERR_INVALID_ARG, "signal too long for one launch");
+        HIP_TRY(launch_toep(p->dt, c.A, a, (int)tiles, stream), "Toeplitz launch");
+        return CWT_OK;
+    }
     const int chunk = pick_chunk(p->dt, p->hop, 128 * c.A, c.chunk);
     const SplitGeo sg = split_geo(p->dt, (int)bk.blocks.size());
     MfmaArgs a;
@@ -958,6 +1069,10 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     // clips have a fixed geometry per (bank, hop, configuration).
     const bool fp32 = p0->dt == DT_FP32;
     int cfg = force_cfg >= 0 ? force_cfg : with_tuned(plans, lens, n, batch_auto_cfg(plans, lens, n));
+    // Clips of Toeplitz plans run Toeplitz tiles of kToepBatchNB blocks per
+    // wave whatever the launch's configuration; the configuration then
+    // describes the batch's other clips (6 when it names Toeplitz tiles).
+    if (!fp32 && kMfmaCfgs[cfg].toep) cfg = 6;
     MfmaCfg c = kMfmaCfgs[fp32 ? 0 : cfg];
     bool cached_ok = true;   // plans[i]->lay is valid for this launch when plans[i]->cfg == cfg
     int chunk = 8;
@@ -967,6 +1082,10 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
         all_win = true;
         for (int i = 0; i < n && !fp32; ++i)
             if (lens[i] > 0) {
+                if (plan_toep(plans[i])) {
+                    all_win = false;   // the every-layout kernel runs Toeplitz tiles
+                    continue;
+                }
                 const ClipLayout& L = plans[i]->cfg == cfg ? plans[i]->lay
                                       : clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk);
                 any_linear = any_linear || L.s.mode == STAGE_LINEAR;
@@ -991,13 +1110,14 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
         cached_ok = false;
         any_linear = false;
         for (int i = 0; i < n; ++i)
-            if (lens[i] > 0) any_linear = any_linear || clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk).s.mode == STAGE_LINEAR;
+            if (lens[i] > 0 && !plan_toep(plans[i]))
+                any_linear = any_linear || clip_layout(p0->dt, bk, plans[i]->hop, c, c.chunk).s.mode == STAGE_LINEAR;
     }
     if (any_linear) {
         for (int ch = c.chunk; ch >= 8; ch -= 8) {
             int64_t mb = 0, mr = 0;
             for (int i = 0; i < n; ++i) {
-                if (lens[i] == 0) continue;
+                if (lens[i] == 0 || plan_toep(plans[i])) continue;
                 const ClipLayout L = clip_layout(p0->dt, bk, plans[i]->hop, c, ch);
                 if (L.s.mode != STAGE_LINEAR) continue;
                 mb = std::max(mb, L.s.bytes);
@@ -1022,10 +1142,11 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     for (int j = 0; j < nc; ++j) {
         const int i = sc.order[j];
         ClipLayout L;
-        sc.clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], c, cached_ok && plans[i]->cfg == cfg, chunk, &L,
-                                &sc.ctiles[i]);
+        const bool tp = plan_toep(plans[i]);
+        sc.clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], tp ? kMfmaCfgs[kToepBatchCfg] : c,
+                                !tp && cached_ok && plans[i]->cfg == cfg, chunk, &L, &sc.ctiles[i]);
         if (fp32) continue;
-        if (L.s.mode == STAGE_WIN) {
+        if (L.s.mode == STAGE_WIN || L.s.mode == STAGE_TOEP) {
             maxwin = std::max(maxwin, L.s.bytes);
         } else {
             maxbuf = std::max(maxbuf, L.s.bytes);
@@ -1081,6 +1202,13 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     a.xcd_remap = 0;
     a.nclips = nc;
     a.total_tiles = (int32_t)total;
+    bool any_toep = false;
+    for (int j = 0; j < nc; ++j) any_toep = any_toep || hc[j].mode == STAGE_TOEP;
+    if (any_toep) {   // the bank's Toeplitz part is built (a Toeplitz plan exists)
+        a.tfrags = bk.d_tfrags;
+        a.tgroups = bk.d_tgroups;
+        a.ntgroups = (int)bk.tgroups.size();
+    }
     // WIN-only batches run the kernel compiled for the WIN register budget.
     bool win_only = true;
     for (int j = 0; j < nc; ++j) win_only = win_only && hc[j].mode == STAGE_WIN;
@@ -1088,6 +1216,7 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     int64_t groups_lcm = 1;
     for (int j = 0; j < nc; ++j) {
         const int64_t ng = hc[j].mode == STAGE_WIN ? (a.ngroups + hc[j].wb - 1) / hc[j].wb
+                           : hc[j].mode == STAGE_TOEP ? a.ntgroups
                            : hc[j].mode == STAGE_LINEAR ? a.ngroups : sg.groups;
         groups_lcm = groups_lcm / gcd64(groups_lcm, ng) * ng;
         if (groups_lcm > 4096) groups_lcm = 4096;   // bounded: a heuristic, not a requirement
@@ -1283,8 +1412,12 @@ cwt_status cwt_plan_create(double fs, cwt_wavelet wavelet, const double* scales,
             std::call_once(attr_once, [&] { ae = mfma_init_attributes(); });
             if (ae != hipSuccess) return fail(CWT_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(ae));
         }
+        if (hop == 1 && (p->dt == DT_BF16 || p->dt == DT_FP16) && toep_fits(*p->bank, 1)) {
+            st = ensure_toep(*p->bank);
+            if (st != CWT_OK) return st;
+        }
         set_cfg(p.get(), default_cfg(p.get(), hop));
-        if (p->cfg == 6) set_auto(p.get());
+        if (p->cfg == 6 || p->cfg == kToepCfg0) set_auto(p.get());
         ensure_tuned_loaded();   // here, so that no launch reads the cache file
         // an automatic plan's 6 stands for the per-launch choice (auto_cfg)
         if (!p->cfg_auto && !cfg_fits(p.get(), p->cfg, hop)) {
@@ -1455,10 +1588,18 @@ int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips) {
     if (!plan || len < 1 || n_clips < 1) return -1;
     if (plan->dt == DT_FP32) return plan->cfg;
     const int64_t K = (len + plan->hop - 1) / plan->hop;
+    if (n_clips > 1 && plan_toep(plan)) return kToepBatchCfg;   // batches run one Toeplitz tile size
     const int cfg = auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups * n_clips; });
     std::vector<cwt_plan_t> pl(n_clips, plan);
     std::vector<int64_t> ln(n_clips, len);
     return with_tuned(pl.data(), ln.data(), n_clips, cfg);
+}
+
+int32_t cwt_plan_config_kind(cwt_plan_t plan, int32_t index) {
+    if (!plan) return -1;
+    if (plan->dt == DT_FP32) return index == 0 ? 0 : -1;
+    if (index < 0 || index >= kNumMfmaCfgs) return -1;
+    return kMfmaCfgs[index].toep ? 1 : 0;
 }
 int32_t cwt_plan_num_configs(cwt_plan_t plan) {
     if (!plan) return -1;
@@ -1571,14 +1712,18 @@ cwt_status cwt_autotune_batch(const cwt_plan_t* plans, const int64_t* lens, int3
                 reps *= 4;
             }
         };
-        // candidates: the automatic choice, then every configuration that
-        // fits every clip's hop
+        // candidates: the automatic choice, then every configuration of its
+        // formulation (scale-block or Toeplitz tiles, whose results differ by
+        // rounding) that fits every clip's hop; a batch's Toeplitz clips run
+        // one tile size, so only its other clips have a choice
         float auto_ms = 0;
         st = time_cfg(auto_choice, &auto_ms);
         if (st != CWT_OK) return st;
         int best = -1;
         float best_ms = auto_ms;
+        const int kind = kMfmaCfgs[auto_choice].toep;
         for (int c = 0; c < kNumMfmaCfgs; ++c) {
+            if (kMfmaCfgs[c].toep != kind || (kind && n > 1)) continue;
             bool ok = true;
             for (int i = 0; i < n && ok; ++i) ok = cfg_fits(plans[i], c, plans[i]->hop);
             if (!ok) continue;

@@ -1044,6 +1044,156 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Toeplitz tiles (hop 1, BF16/FP16).  For one scale (taps t[m], |m| <= M) and
+// the 1024 frames k = k1 + 32 i + j (i, j < 32) of a block:
+//     W[k] = sum_p t[p - j] * x~[k1 + 32 i + p],   p = jb + 16 d + u  (u < 16),
+// so every K-step d is one MFMA  C[i][j] += X_d[i][u] * T_d[u][j]  with
+//     X_d[i][u] = x~[k1 + 32 i + jb + 16 d + u]   (strided rows of the staged
+//                 window: a lane reads 8 consecutive samples, 16-byte aligned)
+//     T_d[u][j] = t[jb + 16 d + u - j]             (a Toeplitz block of the taps,
+//                 stored in the bank in the B operand's lane order).
+// The signal fragment of a step serves every scale of the wave and the tap
+// fragment every block, so a wave holding kToepScales scales x NB blocks
+// issues kToepScales * NB MFMAs per kToepScales + NB fragment loads (the
+// 32-scale blocks of the other tiles share one tap fragment between at most
+// A frame blocks and pad every scale to its block's widest range).  The K
+// range of a scale group starts at jb (<= -M, a multiple of 8) and spans D
+// steps (jb + 16 D >= M + 32, D a multiple of 4); every coefficient adds its
+// steps in ascending d in one accumulator, so the result depends neither on
+// NB nor on the launch.  A work-group (4 waves) owns 4 * 1024 * NB
+// consecutive frames of one clip and one scale group.
+
+// 16-byte unit u of a Toeplitz window sits at LDS unit u ^ ((u >> 4) & 3):
+// the eight lanes of a 128-bit read pass, 4 units apart, then fall on eight
+// different 16-byte slots of a 256-byte bank row instead of four.
+__device__ __forceinline__ int toep_swz(int u) { return u ^ ((u >> 4) & 3); }
+
+// x~[j0 + 8 u .. j0 + 8 u + 8) converted to the operand type, for u < nunits;
+// four units per thread in flight.
+template <int DT>
+__device__ __forceinline__ void toep_stage(const ClipArg& c, int64_t j0, int nunits, bool al16, uint8_t* lds) {
+    constexpr int R = 4;
+    for (int u0 = threadIdx.x; u0 < nunits; u0 += R * kMfmaWaves * kWaveSize) {
+        float v[R][8];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int u = u0 + i * kMfmaWaves * kWaveSize;
+            if (u < nunits) load_span<8, 0>(c.x, c.len, j0 + 8 * (int64_t)u, al16, v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int u = u0 + i * kMfmaWaves * kWaveSize;
+            if (u < nunits) {
+                Packed<DT, 8> pk;
+                pack_span<DT, 8, 0>(v[i], 1.0f, pk);
+                *(i32x4*)(lds + toep_swz(u) * 16) = window<DT, 8, 0>(pk, 0);
+            }
+        }
+    }
+}
+
+template <int DT, int NB>
+__device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
+                                                  uint8_t* lds) {
+    static_assert(DT == DT_BF16 || DT == DT_FP16, "Toeplitz tiles hold 16-bit operands");
+    constexpr int TS = kToepScales;
+    constexpr int FW = 1024 * NB;   // frames per wave
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const ToepGroup* __restrict__ G = a.tgroups + grp;
+    const int jb = G->jb, D = G->D;
+    const int64_t k0 = (int64_t)tile * (kMfmaWaves * FW);
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
+    toep_stage<DT>(c, k0 + jb, (kMfmaWaves * FW + 16 * D) / 8, al16, lds);
+    lds_barrier();
+    const int64_t kw = k0 + (int64_t)w * FW;
+    if (kw >= c.K) return;   // the clip ends before this wave's frames
+
+    const uint8_t* __restrict__ tb = a.tfrags + G->frag_off + lane * 16;
+    // unit of step 0, block 0 of this lane: row i = lane % 32 of the A
+    // operand, K half lane / 32 (8 samples = one 16-byte unit)
+    const int ubase = (w * FW) / 8 + 4 * (lane & 31) + (lane >> 5);
+    i32x4 tp[4][TS];
+    i32x4 sg[2][NB];
+    f32x16 acc[TS][NB];
+#pragma unroll
+    for (int s = 0; s < TS; ++s)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[s][b][v] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(tb + (int64_t)(TS * j + s) * 1024);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sg[0][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b) * 16);
+    for (int d0 = 0; d0 < D; d0 += 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int d = d0 + j;
+            // the next step's signal rows (step D, read last, lies inside the
+            // window), issued first so that they land during this step's MFMAs
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                sg[(j + 1) & 1][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b + 2 * (d + 1)) * 16);
+#pragma unroll
+            for (int s = 0; s < TS; ++s)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[s][b] = mma<DT>(&sg[j & 1][b], &tp[j][s], acc[s][b]);
+            // taps four steps ahead into the registers this step consumed
+            const int dn = min(d + 4, D - 1);
+#pragma unroll
+            for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(tb + (int64_t)(TS * dn + s) * 1024);
+            // pin that order (left alone, the scheduler sinks every load next
+            // to its first use and waits for it there)
+            __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);        // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, TS * NB, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, TS, 0);        // VMEM read
+        }
+    }
+    // Epilogue: lane column j = lane % 32, rows i = 8 (v / 4) + 4 (lane / 32) + v % 4:
+    // for each v the 32 lanes of a half-wave store 32 consecutive frames.
+    const int r = lane & 31, hg = lane >> 5;
+#pragma unroll
+    for (int s = 0; s < TS; ++s) {
+        const int row = G->rows[s];
+        if (row < 0) continue;
+        float* __restrict__ orow = c.out + (int64_t)row * c.K;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int64_t kb0 = kw + 1024 * b + r;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t k = kb0 + 32 * (8 * (v >> 2) + 4 * hg + (v & 3));
+                if (k < c.K) {
+                    float val = acc[s][b][v];
+                    if (!a.signed_out) val = fabsf(val);
+                    __builtin_nontemporal_store(val, orow + k);
+                }
+            }
+        }
+    }
+}
+
+// Work-group id -> (scale group, frame tile).  Work-groups are dealt to the 8
+// XCDs round-robin; when the group count is a multiple of 8, XCD x takes one
+// group of every eight (snake order, so the XCDs' K ranges balance) and runs
+// its groups widest first, each over all its frame tiles: a group's tap
+// fragments then stay in one XCD's L2.  Groups are stored narrowest first.
+__device__ __forceinline__ void toep_unit(int id, int ntg, int ntile, int* grp, int* tile) {
+    if ((ntg & 7) == 0) {
+        const int x = id & 7, slot = id >> 3;
+        const int oct = ntg / 8 - 1 - slot / ntile;   // widest octet first
+        *tile = slot % ntile;
+        *grp = 8 * oct + ((oct & 1) ? 7 - x : x);
+    } else {
+        *grp = ntg - 1 - id / ntile;
+        *tile = id % ntile;
+    }
+}
+
 __device__ __forceinline__ int xcd_remap(int id, int n) {
     // Work-groups are dealt to the 8 XCDs round-robin; give each XCD a
     // contiguous range of tiles so neighbouring tiles share its L2.
@@ -1085,6 +1235,15 @@ void k_mfma_win(MfmaArgs a) {
     process_tile_win<DT, A>(a, a.clip, tile, grp, lds, red);
 }
 
+// Toeplitz tiles of one clip: grid = scale groups x frame tiles.
+template <int DT, int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_toep(MfmaArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    int grp, tile;
+    toep_unit(blockIdx.x, a.ntgroups, a.clip.ntile, &grp, &tile);
+    process_tile_toep<DT, NB>(a, a.clip, tile, grp, lds);
+}
+
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
 // (G = gridDim.x, every work-group resident) with no atomics; the host picks G
 // coprime with the number of block groups so that a work-group's tiles rotate
@@ -1112,6 +1271,15 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
         const int local = t - (in_lds ? spre[lo] : a.tile_prefix[lo]);
         const ClipArg c = a.clips[lo];
         if constexpr (ANY) {
+            if constexpr (DT == DT_BF16 || DT == DT_FP16) {
+                if (c.mode == STAGE_TOEP) {
+                    int grp, tile;
+                    toep_unit(local, a.ntgroups, c.ntile, &grp, &tile);
+                    process_tile_toep<DT, kToepBatchNB>(a, c, tile, grp, lds);
+                    lds_barrier();
+                    continue;
+                }
+            }
             if (c.mode == STAGE_LINEAR) {
                 const int tile = local / a.ngroups, blk = local - tile * a.ngroups;
                 process_tile<DT, A>(a, c, tile, blk, lds, red);
@@ -1230,8 +1398,19 @@ static hipError_t attrs1() {
     return e;
 }
 
+template <int DT, int NB>
+static hipError_t toep_attr() {
+    return hipFuncSetAttribute((const void*)k_toep<DT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds_max());
+}
+
 hipError_t mfma_init_attributes() {
-    hipError_t e = attrs1<DT_BF16>();
+    hipError_t e = toep_attr<DT_BF16, 1>();
+    if (e == hipSuccess) e = toep_attr<DT_BF16, 2>();
+    if (e == hipSuccess) e = toep_attr<DT_BF16, 4>();
+    if (e == hipSuccess) e = toep_attr<DT_FP16, 1>();
+    if (e == hipSuccess) e = toep_attr<DT_FP16, 2>();
+    if (e == hipSuccess) e = toep_attr<DT_FP16, 4>();
+    if (e == hipSuccess) e = attrs1<DT_BF16>();
     if (e == hipSuccess) e = attrs1<DT_FP16>();
     if (e == hipSuccess) e = attrs1<DT_BF16X3>();
     if (e == hipSuccess) e = attrs1<DT_FP8>();
@@ -1260,6 +1439,49 @@ hipError_t launch_mfma(int dt, int A, int, const MfmaArgs& a, int persistent, in
 }
 
 int mfma_max_lds_bytes() { return 160 * 1024; }
+
+template <int DT, int NB>
+static hipError_t launch_toep2(const MfmaArgs& a, int grid, hipStream_t s) {
+    if ((size_t)a.shm_bytes > (size_t)dyn_lds_max()) return hipErrorInvalidValue;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_toep<DT, NB>), dim3(grid), dim3(256), (size_t)a.shm_bytes, s, a);
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t launch_toep1(int NB, const MfmaArgs& a, int grid, hipStream_t s) {
+    switch (NB) {
+        case 1: return launch_toep2<DT, 1>(a, grid, s);
+        case 2: return launch_toep2<DT, 2>(a, grid, s);
+        case 4: return launch_toep2<DT, 4>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_toep(int dt, int NB, const MfmaArgs& a, int grid, hipStream_t s) {
+    switch (dt) {
+        case DT_BF16: return launch_toep1<DT_BF16>(NB, a, grid, s);
+        case DT_FP16: return launch_toep1<DT_FP16>(NB, a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int DT, int NB>
+static int toep_occ2(size_t shm) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_toep<DT, NB>, 256, shm) != hipSuccess) return 1;
+    return n;
+}
+
+int toep_occupancy(int dt, int NB, size_t shm) {
+    if (dt != DT_BF16 && dt != DT_FP16) return 1;
+    const bool h = dt == DT_FP16;
+    switch (NB) {
+        case 1: return h ? toep_occ2<DT_FP16, 1>(shm) : toep_occ2<DT_BF16, 1>(shm);
+        case 2: return h ? toep_occ2<DT_FP16, 2>(shm) : toep_occ2<DT_BF16, 2>(shm);
+        default: return h ? toep_occ2<DT_FP16, 4>(shm) : toep_occ2<DT_BF16, 4>(shm);
+    }
+}
 
 template <int DT, int A>
 static int occ2(int persistent, size_t shm) {

@@ -42,6 +42,7 @@ _SIGS = {
     "cwt_autotune_batch": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "cwt_plan_config": (_i32, [_c_plan]),
     "cwt_plan_num_configs": (_i32, [_c_plan]),
+    "cwt_plan_config_kind": (_i32, [_c_plan, _i32]),
     "cwt_plan_launch_config": (_i32, [_c_plan, _i64, _i32]),
     "cwt_plan_set_config": (_i32, [_c_plan, _i32]),
     "cwt_plan_bank_taps": (_i32, [_c_plan, _i32, _vp, _i64]),
@@ -192,6 +193,10 @@ class Plan:
     def launch_config(self, n: int, clips: int = 1) -> int:
         """The configuration a launch of `clips` clips of n samples runs."""
         return int(_lib.cwt_plan_launch_config(self._h, int(n), int(clips)))
+
+    def config_kind(self, i: int) -> int:
+        """0: 32-scale-block tiles, 1: Toeplitz tiles (hop 1), -1: none."""
+        return int(_lib.cwt_plan_config_kind(self._h, int(i)))
 
     @property
     def num_configs(self) -> int:

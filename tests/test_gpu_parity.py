@@ -348,6 +348,9 @@ def test_impulse_response_on_device(torch, cw, dt):
 
 @pytest.mark.parametrize("dt", ["bf16", "fp16", "bf16x3", "fp8", "fp32"])
 def test_bitwise_repeatable_and_config_independent(torch, cw, dt):
+    """Bit-identical run to run and across the configurations of one kind;
+    the two kinds (32-scale-block and, at hop 1, Toeplitz tiles) group each
+    coefficient's products differently and agree within the tolerance."""
     x = clip(2, 1, 160000, 0.0)
     xd = torch.from_numpy(x).cuda()
     for hop in (1, 3, 256, 384):
@@ -356,12 +359,22 @@ def test_bitwise_repeatable_and_config_independent(torch, cw, dt):
         b = p(xd)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+        first = {p.config_kind(p.config): a}
         for c in range(p.num_configs):
             try:
                 p.set_config(c)
             except cw.CwtError:
                 continue
-            assert torch.equal(p(xd), a), (dt, hop, c)
+            got = p(xd)
+            kind = p.config_kind(c)
+            if kind in first:
+                assert torch.equal(got, first[kind]), (dt, hop, c)
+            else:
+                first[kind] = got
+        if len(first) > 1:
+            assert_close(dt, first[0].cpu().numpy(), first[1].cpu().numpy(), "hop %d block vs Toeplitz tiles" % hop)
+        if dt in ("bf16", "fp16"):
+            assert (hop == 1) == (1 in first), (dt, hop, sorted(first))
 
 
 # ---------------------------------------------------------------------------
@@ -589,7 +602,10 @@ def test_launch_configuration_follows_the_launch(torch, cw):
     not fit LDS), 32-frame tiles for one clip there (too few frames); a set
     configuration holds for every launch, and the results agree bit for bit."""
     scales = np.arange(1, 129)
-    assert cw.Plan(16000.0, scales, 1, "bf16").launch_config(160000) == 6
+    p1 = cw.Plan(16000.0, scales, 1, "bf16")
+    assert p1.config_kind(p1.launch_config(160000)) == 1          # hop 1: Toeplitz tiles
+    assert p1.launch_config(160000, 3) == 14                       # the batch tile size
+    assert cw.Plan(16000.0, scales, 1, "bf16x3").config_kind(6) == 0
     p = cw.Plan(16000.0, scales, 512, "bf16", signed=True)
     assert p.config == 6
     assert p.launch_config(160000, 256) == 4 and p.launch_config(160000, 1) == 5
