@@ -62,11 +62,19 @@ struct MfmaBlock {
 // per step.
 constexpr int kToepScales = 2;
 constexpr int kToepBatchNB = 2;    // 1024-frame blocks per wave in batch tiles
+constexpr int kToepPrefetch = 8;   // K-steps between a tap fragment's load and its use (single-clip launches)
 // First p and K-steps of a group whose widest scale has half-width M, and the
 // LDS window (2-byte operands) of a tile of 4 * 1024 * NB frames over D steps.
 __host__ __device__ constexpr int toep_jb(int M) { return -8 * ((M + 7) / 8); }
 __host__ __device__ constexpr int toep_steps(int M) { return (((M + 32 - toep_jb(M) + 15) / 16) + 3) & ~3; }
 __host__ __device__ constexpr int toep_window_bytes(int NB, int D) { return (kMfmaWaves * 1024 * NB + 16 * D) * 2; }
+// 16-byte units of the window of a work-group running group (jb0, D0) and,
+// if D1 > 0, a narrower group (jb1 >= jb0, D1) after it: every step of both,
+// plus the signal rows read one step past the last, rounded up to whole
+// groups of four units (the XOR swizzle permutes within them).
+__host__ __device__ constexpr int toep_window_units(int NB, int jb0, int D0, int jb1, int D1) {
+    return (512 * NB + (2 * D0 > 2 * D1 + (jb1 - jb0) / 8 ? 2 * D0 : 2 * D1 + (jb1 - jb0) / 8) + 3) & ~3;
+}
 struct ToepGroup {
     int32_t jb;            // first p of step 0: a multiple of 8, <= -M of every scale
     int32_t D;             // K-steps (a multiple of 4); jb + 16 D >= M + 32
@@ -115,6 +123,7 @@ struct MfmaArgs {
     const uint8_t* tfrags;
     const ToepGroup* tgroups;
     int32_t ntgroups;
+    int32_t toep_bg;       // scale groups per Toeplitz work-group: 1, or 2 (group ng-1-u with group u)
     // single clip (grid launch)
     ClipArg clip;
     // batch (persistent launch)

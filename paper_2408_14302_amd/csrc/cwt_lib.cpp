@@ -113,9 +113,14 @@ static const MfmaCfg kMfmaCfgs[] = {
     {8, 4, 4, 32},   // 10: 256 frames, one block per wave (WIN only, BF16/FP16)
     {8, 4, 2, 32},   // 11: 512 frames, blocks {0,3} / {1,2} per wave (WIN only, BF16/FP16)
     {8, 4, 1, 32},   // 12: 1024 frames, every wave runs all 4 blocks (WIN only, BF16/FP16)
-    {4, 0, 0, 0, 1}, // 13: Toeplitz, 16384 frames x one scale pair per work-group (hop 1, BF16/FP16)
-    {2, 0, 0, 0, 1}, // 14: Toeplitz, 8192 frames
-    {1, 0, 0, 0, 1}, // 15: Toeplitz, 4096 frames
+    // Toeplitz tiles (hop 1, BF16/FP16): A = 1024-frame blocks per wave, wb =
+    // scale groups (of two scales) per work-group, the widest with the narrowest
+    {4, 1, 0, 0, 1}, // 13: Toeplitz, 16384 frames x one scale group per work-group
+    {2, 1, 0, 0, 1}, // 14: Toeplitz, 8192 frames
+    {1, 1, 0, 0, 1}, // 15: Toeplitz, 4096 frames
+    {4, 2, 0, 0, 1}, // 16: Toeplitz, 16384 frames x two groups over one window
+    {2, 2, 0, 0, 1}, // 17: Toeplitz, 8192 frames x two groups
+    {1, 2, 0, 0, 1}, // 18: Toeplitz, 4096 frames x two groups
 };
 static const int kToepCfg0 = 13;   // the Toeplitz configurations are 13 .. 15
 static const int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
@@ -278,6 +283,7 @@ struct Bank {
     ToepGroup* d_tgroups = nullptr;
     uint8_t* d_tfrags = nullptr;
     int toep_Dmax = 0;
+    int toep_w1 = 0, toep_w2 = 0;   // window units beyond the frames: one group, a bundle of two
 
     ~Bank() {
         if (d_tgroups) (void)hipFree(d_tgroups);
@@ -426,7 +432,12 @@ static cwt_status acquire_bank(int dt, int device, const std::vector<double>& sc
 }
 
 // Toeplitz windows must fit the WIN budget at one block per wave.
-static bool toep_fits(const Bank& bk, int NB) { return toep_window_bytes(NB, toep_steps(bk.Mmax)) <= kWinBudget; }
+// LDS bytes of a Toeplitz work-group of the bank (its widest group, or its
+// widest bundle of two), and whether it fits the WIN budget.
+static int64_t toep_bytes(const Bank& bk, int NB, int bg) {
+    return 16 * (int64_t)((512 * NB + (bg == 2 ? bk.toep_w2 : bk.toep_w1) + 3) & ~3);
+}
+static bool toep_fits(const Bank& bk, int NB) { return toep_window_bytes(NB, toep_steps(bk.Mmax)) + 64 <= kWinBudget; }
 
 // Build the bank's Toeplitz fragments once (BF16/FP16 banks whose widest
 // window fits): groups of kToepScales consecutive sorted scales, jb = -M of
@@ -466,8 +477,20 @@ static cwt_status ensure_toep(Bank& bk) {
     HIP_TRY(hipMemcpy(bk.d_tgroups, gs.data(), sizeof(ToepGroup) * ng, hipMemcpyHostToDevice), "Toeplitz groups copy");
     HIP_TRY(gen_toep_bank(bk.dt, d_sorted, S, bk.d_tgroups, ng, bk.d_tfrags, 0), "Toeplitz bank generation");
     HIP_TRY(hipDeviceSynchronize(), "Toeplitz bank generation");
+    int w1 = 0, w2 = 0;
+    for (int u = 0; u < ng; ++u) {
+        w1 = std::max(w1, 2 * gs[u].D);
+        const int v = ng - 1 - u;   // a bundle runs group v (the wider) and u
+        if (u <= v) {
+            int w = 2 * gs[v].D;
+            if (u < v) w = std::max(w, 2 * gs[u].D + (gs[u].jb - gs[v].jb) / 8);
+            w2 = std::max(w2, w);
+        }
+    }
     bk.tgroups = std::move(gs);
     bk.toep_Dmax = dmax;
+    bk.toep_w1 = w1;
+    bk.toep_w2 = w2;
     bk.toep_built = true;
     return CWT_OK;
 }
@@ -664,7 +687,8 @@ static bool cfg_fits(const cwt_plan_s* p, int cfg, int hop) {
     // Toeplitz tiles: hop 1, 16-bit operands, a built Toeplitz bank whose
     // widest window fits at this tile size
     if (c.toep)
-        return hop == 1 && (p->dt == DT_BF16 || p->dt == DT_FP16) && p->bank->toep_built && toep_fits(*p->bank, c.A);
+        return hop == 1 && (p->dt == DT_BF16 || p->dt == DT_FP16) && p->bank->toep_built &&
+               toep_bytes(*p->bank, c.A, c.wb) <= kWinBudget;
     // FP8 scales the signal per 128-frame segment up to hop 128 (fp8_beta):
     // every tile must lie in one segment, i.e. have at most 128 frames.
     // Configuration 5 (32-frame WIN, 128-frame chunked and 32-128-frame row
@@ -690,15 +714,16 @@ static ClipLayout clip_layout(int dt, const Bank& bk, int hop, const MfmaCfg& c,
     if (c.toep) {
         // Toeplitz tiles for hop-1 clips of a built bank; any other clip of a
         // launch under a Toeplitz configuration takes configuration 6's tiles
-        if (hop == 1 && bk.toep_built && toep_fits(bk, c.A)) {
+        if (hop == 1 && bk.toep_built && toep_bytes(bk, c.A, c.wb) <= kWinBudget) {
             L.s.mode = STAGE_TOEP;
             L.s.copies = 1;
             L.s.swz = -1;
             L.s.cso = 0;
-            L.s.bytes = toep_window_bytes(c.A, bk.toep_Dmax);
+            L.s.bytes = toep_bytes(bk, c.A, c.wb);
             L.s.raw_bytes = 0;
             L.F = kMfmaWaves * 1024 * c.A;
-            L.groups = (int64_t)bk.tgroups.size();
+            L.wb = c.wb;
+            L.groups = c.wb == 2 ? ((int64_t)bk.tgroups.size() + 1) / 2 : (int64_t)bk.tgroups.size();
             return L;
         }
         const MfmaCfg& h = kMfmaCfgs[6];
@@ -890,6 +915,7 @@ static cwt_status launch_one(const cwt_plan_s* p, int cfg, const float* x, int64
         a.tfrags = bk.d_tfrags;
         a.tgroups = bk.d_tgroups;
         a.ntgroups = (int)bk.tgroups.size();
+        a.toep_bg = c.wb;
         ClipLayout L;
         a.clip = make_clip(p, x, len, out, c, cfg == p->cfg, 8, &L, &tiles);
         if (L.s.mode != STAGE_TOEP) return fail(CWT_ERR_INTERNAL, "Toeplitz configuration without Toeplitz tiles");
@@ -1208,6 +1234,7 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
         a.tfrags = bk.d_tfrags;
         a.tgroups = bk.d_tgroups;
         a.ntgroups = (int)bk.tgroups.size();
+        a.toep_bg = kMfmaCfgs[kToepBatchCfg].wb;
     }
     // WIN-only batches run the kernel compiled for the WIN register budget.
     bool win_only = true;
@@ -1216,7 +1243,7 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     int64_t groups_lcm = 1;
     for (int j = 0; j < nc; ++j) {
         const int64_t ng = hc[j].mode == STAGE_WIN ? (a.ngroups + hc[j].wb - 1) / hc[j].wb
-                           : hc[j].mode == STAGE_TOEP ? a.ntgroups
+                           : hc[j].mode == STAGE_TOEP ? (a.toep_bg == 2 ? (a.ntgroups + 1) / 2 : a.ntgroups)
                            : hc[j].mode == STAGE_LINEAR ? a.ngroups : sg.groups;
         groups_lcm = groups_lcm / gcd64(groups_lcm, ng) * ng;
         if (groups_lcm > 4096) groups_lcm = 4096;   // bounded: a heuristic, not a requirement

@@ -1093,28 +1093,21 @@ __device__ __forceinline__ void toep_stage(const ClipArg& c, int64_t j0, int nun
     }
 }
 
-template <int DT, int NB>
-__device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipArg& c, int tile, int grp,
-                                                  uint8_t* lds) {
-    static_assert(DT == DT_BF16 || DT == DT_FP16, "Toeplitz tiles hold 16-bit operands");
+// The K loop and epilogue of one scale group over the wave's frames
+// kw .. kw + 1024 NB - 1, from the staged window (16-byte unit ubase is row
+// i = lane % 32, K half lane / 32, of step 0, block 0).  tp holds the group's
+// first PF steps of tap fragments on entry; `next`, when not null, is the
+// group run after this one: its first PF steps are loaded into tp right
+// after the loop, ahead of this group's stores.
+template <int DT, int NB, int PF>
+__device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, const ToepGroup* __restrict__ G,
+                                           const ToepGroup* __restrict__ next, int64_t kw, int ubase,
+                                           const uint8_t* lds, i32x4 (&tp)[PF][kToepScales]) {
     constexpr int TS = kToepScales;
-    constexpr int FW = 1024 * NB;   // frames per wave
+    static_assert(PF == 4 || PF == 8, "prefetch depth of 4 or 8 steps");
     const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const ToepGroup* __restrict__ G = a.tgroups + grp;
-    const int jb = G->jb, D = G->D;
-    const int64_t k0 = (int64_t)tile * (kMfmaWaves * FW);
-    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
-    toep_stage<DT>(c, k0 + jb, (kMfmaWaves * FW + 16 * D) / 8, al16, lds);
-    lds_barrier();
-    const int64_t kw = k0 + (int64_t)w * FW;
-    if (kw >= c.K) return;   // the clip ends before this wave's frames
-
+    const int D = G->D;
     const uint8_t* __restrict__ tb = a.tfrags + G->frag_off + lane * 16;
-    // unit of step 0, block 0 of this lane: row i = lane % 32 of the A
-    // operand, K half lane / 32 (8 samples = one 16-byte unit)
-    const int ubase = (w * FW) / 8 + 4 * (lane & 31) + (lane >> 5);
-    i32x4 tp[4][TS];
     i32x4 sg[2][NB];
     f32x16 acc[TS][NB];
 #pragma unroll
@@ -1124,34 +1117,44 @@ __device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipA
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[s][b][v] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(tb + (int64_t)(TS * j + s) * 1024);
-#pragma unroll
     for (int b = 0; b < NB; ++b) sg[0][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b) * 16);
-    for (int d0 = 0; d0 < D; d0 += 4) {
+    // one K-step d in tap slot j (= d mod PF) and signal buffer j & 1
+    auto step = [&](const int j, const int d) __attribute__((always_inline)) {
+        // the next step's signal rows (step D, read last, lies inside the
+        // window), issued first so that they land during this step's MFMAs
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int d = d0 + j;
-            // the next step's signal rows (step D, read last, lies inside the
-            // window), issued first so that they land during this step's MFMAs
+        for (int b = 0; b < NB; ++b)
+            sg[(j + 1) & 1][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b + 2 * (d + 1)) * 16);
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                sg[(j + 1) & 1][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b + 2 * (d + 1)) * 16);
+        for (int s = 0; s < TS; ++s)
 #pragma unroll
-            for (int s = 0; s < TS; ++s)
+            for (int b = 0; b < NB; ++b) acc[s][b] = mma<DT>(&sg[j & 1][b], &tp[j][s], acc[s][b]);
+        // taps PF steps ahead into the registers this step consumed
+        const int dn = min(d + PF, D - 1);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) acc[s][b] = mma<DT>(&sg[j & 1][b], &tp[j][s], acc[s][b]);
-            // taps four steps ahead into the registers this step consumed
-            const int dn = min(d + 4, D - 1);
+        for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(tb + (int64_t)(TS * dn + s) * 1024);
+        // pin that order (left alone, the scheduler sinks every load next to
+        // its first use and waits for it there)
+        __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);        // DS read
+        __builtin_amdgcn_sched_group_barrier(0x008, TS * NB, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x020, TS, 0);        // VMEM read
+    };
+    int d0 = 0;
+    for (; d0 + PF <= D; d0 += PF) {
 #pragma unroll
-            for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(tb + (int64_t)(TS * dn + s) * 1024);
-            // pin that order (left alone, the scheduler sinks every load next
-            // to its first use and waits for it there)
-            __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);        // DS read
-            __builtin_amdgcn_sched_group_barrier(0x008, TS * NB, 0);   // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x020, TS, 0);        // VMEM read
-        }
+        for (int j = 0; j < PF; ++j) step(j, d0 + j);
+    }
+    if (d0 < D) {   // D is a multiple of 4: a last half round (PF = 8)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) step(j, d0 + j);
+    }
+    if (next) {
+        const uint8_t* __restrict__ nb = a.tfrags + next->frag_off + lane * 16;
+        const int Dn = next->D;
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+#pragma unroll
+            for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(nb + (int64_t)(TS * min(j, Dn - 1) + s) * 1024);
     }
     // Epilogue: lane column j = lane % 32, rows i = 8 (v / 4) + 4 (lane / 32) + v % 4:
     // for each v the 32 lanes of a half-wave store 32 consecutive frames.
@@ -1177,20 +1180,68 @@ __device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipA
     }
 }
 
-// Work-group id -> (scale group, frame tile).  Work-groups are dealt to the 8
-// XCDs round-robin; when the group count is a multiple of 8, XCD x takes one
-// group of every eight (snake order, so the XCDs' K ranges balance) and runs
-// its groups widest first, each over all its frame tiles: a group's tap
-// fragments then stay in one XCD's L2.  Groups are stored narrowest first.
-__device__ __forceinline__ void toep_unit(int id, int ntg, int ntile, int* grp, int* tile) {
-    if ((ntg & 7) == 0) {
+// One Toeplitz work-group tile: frames tile * 4096 NB .. of one clip against
+// one scale group, or two (g1 >= 0) run one after the other over one staged
+// window (sized for the wider, g0).
+template <int DT, int NB, int PF>
+__device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipArg& c, int tile, int g0, int g1,
+                                                  uint8_t* lds) {
+    static_assert(DT == DT_BF16 || DT == DT_FP16, "Toeplitz tiles hold 16-bit operands");
+    constexpr int FW = 1024 * NB;   // frames per wave
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const ToepGroup* __restrict__ G0 = a.tgroups + g0;
+    const ToepGroup* __restrict__ G1 = g1 >= 0 ? a.tgroups + g1 : nullptr;
+    const int64_t k0 = (int64_t)tile * (kMfmaWaves * FW);
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
+    // the window starts at g0's jb; g1 (narrower: jb1 >= jb0) reads it from
+    // an offset of (jb1 - jb0) / 8 units, its steps reaching up to 3 units
+    // past g0's (toep_window_units)
+    toep_stage<DT>(c, k0 + G0->jb, toep_window_units(NB, G0->jb, G0->D, G1 ? G1->jb : G0->jb, G1 ? G1->D : 0),
+                   al16, lds);
+    lds_barrier();
+    const int64_t kw = k0 + (int64_t)w * FW;
+    if (kw >= c.K) return;   // the clip ends before this wave's frames
+    const int ubase = (w * FW) / 8 + 4 * (lane & 31) + (lane >> 5);
+    i32x4 tp[PF][kToepScales];
+    {
+        const uint8_t* __restrict__ tb = a.tfrags + G0->frag_off + lane * 16;
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+#pragma unroll
+            for (int s = 0; s < kToepScales; ++s)
+                tp[j][s] = *(const i32x4*)(tb + (int64_t)(kToepScales * min(j, G0->D - 1) + s) * 1024);
+    }
+    toep_group<DT, NB, PF>(a, c, G0, G1, kw, ubase, lds, tp);
+    if (G1) toep_group<DT, NB, PF>(a, c, G1, nullptr, kw, ubase + (G1->jb - G0->jb) / 8, lds, tp);
+}
+
+// Work-group id -> (frame tile, scale groups).  With bundles (bg = 2) a
+// work-group runs group ng-1-u and group u (u < ng/2) over one window: the
+// widest with the narrowest, so every work-group carries about the same K
+// steps.  Work-groups are dealt to the 8 XCDs round-robin; when the unit count
+// (groups, or bundles) is a multiple of 8, XCD x takes every eighth unit
+// (snake order over the groups, so the XCDs' K ranges balance), each over all
+// its frame tiles: a group's tap fragments then stay in one XCD's L2.  Groups
+// are stored narrowest first; single groups run widest first.
+__device__ __forceinline__ void toep_unit(int id, int ntg, int bg, int ntile, int* g0, int* g1, int* tile) {
+    const int nu = bg == 2 ? (ntg + 1) / 2 : ntg;   // units
+    int u;
+    if ((nu & 7) == 0) {
         const int x = id & 7, slot = id >> 3;
-        const int oct = ntg / 8 - 1 - slot / ntile;   // widest octet first
+        const int oct = nu / 8 - 1 - slot / ntile;   // last octet first
         *tile = slot % ntile;
-        *grp = 8 * oct + ((oct & 1) ? 7 - x : x);
+        u = 8 * oct + ((oct & 1) ? 7 - x : x);
     } else {
-        *grp = ntg - 1 - id / ntile;
+        u = nu - 1 - id / ntile;
         *tile = id % ntile;
+    }
+    if (bg == 2) {
+        *g0 = ntg - 1 - u;
+        *g1 = u < ntg - 1 - u ? u : -1;
+    } else {
+        *g0 = u;
+        *g1 = -1;
     }
 }
 
@@ -1239,9 +1290,9 @@ void k_mfma_win(MfmaArgs a) {
 template <int DT, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_toep(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    int grp, tile;
-    toep_unit(blockIdx.x, a.ntgroups, a.clip.ntile, &grp, &tile);
-    process_tile_toep<DT, NB>(a, a.clip, tile, grp, lds);
+    int g0, g1, tile;
+    toep_unit(blockIdx.x, a.ntgroups, a.toep_bg, a.clip.ntile, &g0, &g1, &tile);
+    process_tile_toep<DT, NB, kToepPrefetch>(a, a.clip, tile, g0, g1, lds);
 }
 
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
@@ -1273,9 +1324,9 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
         if constexpr (ANY) {
             if constexpr (DT == DT_BF16 || DT == DT_FP16) {
                 if (c.mode == STAGE_TOEP) {
-                    int grp, tile;
-                    toep_unit(local, a.ntgroups, c.ntile, &grp, &tile);
-                    process_tile_toep<DT, kToepBatchNB>(a, c, tile, grp, lds);
+                    int g0, g1, tile;
+                    toep_unit(local, a.ntgroups, a.toep_bg, c.ntile, &g0, &g1, &tile);
+                    process_tile_toep<DT, kToepBatchNB, 4>(a, c, tile, g0, g1, lds);
                     lds_barrier();
                     continue;
                 }
