@@ -99,6 +99,7 @@ def parse():
                          "BF16 / FP8 / FP32 (JSON lines)")
     ap.add_argument("--errors", action="store_true",
                     help="error of every path against the FP64 oracle per workload, dtype and hop (JSON lines)")
+    ap.add_argument("--long-dtypes", default="bf16,fp8,fp32", help="paths timed by --long (comma separated)")
     ap.add_argument("--dwt-clips", default="3,256", help="batch sizes for --dwt (comma separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB mebibytes (calibrates HBM byte counters)")
@@ -301,7 +302,7 @@ def long_bench(torch, cwth, synth, dev, args):
     for hop in (128, 512):
         K = -(-n // hop)
         row = {"hop": hop, "channels": ch, "samples": n, "scales": 256, "frames": K}
-        for dt in ("bf16", "fp8", "fp32"):
+        for dt in args.long_dtypes.split(","):
             plan = cwth.Plan(fs, scales, hop, dt)
             B = cwth.Batch(ch)
             sets = [base, [b.clone() for b in base]]
@@ -315,8 +316,10 @@ def long_bench(torch, cwth, synth, dev, args):
             row[dt] = {"ms_per_launch": ms, "coeffs_per_s": ch * 256 * K / (ms * 1e-3), "tflops": tflops,
                        "frac_of_peak": tflops / peaks[dt], "config": plan.launch_config(n, ch)}
             del prep, outs, B, plan
-        row["bf16_over_fp32"] = row["fp32"]["ms_per_launch"] / row["bf16"]["ms_per_launch"]
-        row["fp8_over_bf16"] = row["bf16"]["ms_per_launch"] / row["fp8"]["ms_per_launch"]
+        if "fp32" in row and "bf16" in row:
+            row["bf16_over_fp32"] = row["fp32"]["ms_per_launch"] / row["bf16"]["ms_per_launch"]
+        if "fp8" in row and "bf16" in row:
+            row["fp8_over_bf16"] = row["bf16"]["ms_per_launch"] / row["fp8"]["ms_per_launch"]
         if not args.no_cpu:
             import oracle
             x0 = base[0].cpu().numpy().astype(np.float64)
@@ -326,10 +329,9 @@ def long_bench(torch, cwth, synth, dev, args):
             row["cpu_baseline"] = {"value": 256 * K / sec, "unit": "coeffs/s", "cores": oracle.max_threads(),
                                    "kind": "oracle", "seconds": sec, "sample": "one of the channels, FP64"}
         print(json.dumps({"metric": "8 x 60 s at 48 kHz, 256 geometric scales", **row}), flush=True)
-        log("hop %d: bf16 %.2f ms (%.0f TFLOP/s, %.2f of peak), fp8 %.2f ms (%.2f), fp32 %.1f ms; bf16/fp32 %.1f" % (
-            hop, row["bf16"]["ms_per_launch"], row["bf16"]["tflops"], row["bf16"]["frac_of_peak"],
-            row["fp8"]["ms_per_launch"], row["fp8"]["frac_of_peak"], row["fp32"]["ms_per_launch"],
-            row["bf16_over_fp32"]))
+        log("hop %d: " % hop + ", ".join("%s %.3f ms (%.0f TFLOP/s, %.2f of peak)" % (
+            d, row[d]["ms_per_launch"], row[d]["tflops"], row[d]["frac_of_peak"])
+            for d in args.long_dtypes.split(",")))
 
 
 def dwt_bench(torch, cwth, synth, dev, scales, args):

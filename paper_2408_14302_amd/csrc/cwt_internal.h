@@ -17,10 +17,10 @@ constexpr int kWaveSize = 64;
 constexpr int kMfmaWaves = 4;      // waves per MFMA work-group (split along frames)
 constexpr int kFp8Segment = 128;        // frames per FP8 signal-scale segment (the largest FP8 tile)
 constexpr int kFp8SegmentMaxHop = 128;  // FP8 scales per segment up to this hop, per tile beyond
-constexpr int kDirectFrames = 64;  // frames per direct-sum work-group (one per lane)
-constexpr int kDirectRows = 16;    // scales per direct-sum wave
-constexpr int kDirectWaves = 4;    // waves per direct-sum work-group
-constexpr int kDirectChunk = 128;  // taps staged per LDS chunk in the direct kernel
+constexpr int kDirectWaves = 4;    // waves per direct-sum work-group (64 frames each)
+constexpr int kDirectFrames = 64 * kDirectWaves;  // frames per direct-sum work-group (one per thread)
+constexpr int kDirectRows = 16;    // scales per direct-sum work-group (every wave runs all of them)
+constexpr int kDirectChunk = 32;   // taps staged per LDS chunk in the direct kernel
 
 // K (taps) consumed by one MFMA for the operand type.
 __host__ __device__ constexpr int kstep_of(int dt) { return dt == DT_FP8 ? 64 : 16; }

@@ -874,7 +874,7 @@ static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float
     c.ws = 1;
     if (p->dt == DT_FP32) {
         c.ntile = (int32_t)((c.K + kDirectFrames - 1) / kDirectFrames);
-        if (tiles_out) *tiles_out = (int64_t)c.ntile * (((int64_t)p->bank->dgroups.size() + kDirectWaves - 1) / kDirectWaves);
+        if (tiles_out) *tiles_out = (int64_t)c.ntile * (int64_t)p->bank->dgroups.size();
         return c;
     }
     const bool cached = cached_ok && (p->lay.s.mode != STAGE_LINEAR || chunk == p->lay_chunk);
