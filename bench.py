@@ -35,7 +35,7 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 
-# HBM bytes per launch of the two timed MFMA kernels, from two rocprofv3 --pmc
+# HBM bytes per launch of the three timed MFMA kernels, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over
 # the dispatches of the leg), each scaled by what the counter reads for a plain
 # device copy of known size (FETCH_SCALE, WRITE_SCALE).  They describe the
@@ -44,11 +44,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_mfma_win<1, 2>", "config": 6, "fetch_kib": 1802.22, "write_kib": 80000.01,
-                  "src_sha256": "b24e8253cc5a64d52d1149893497f10fb6b62c5e0b5514b437e47a47cac2829d"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87360.46,
-                    "write_kib": 56086.55,
-                    "src_sha256": "b24e8253cc5a64d52d1149893497f10fb6b62c5e0b5514b437e47a47cac2829d"},
+    "bf16_hop1": {"kernel": "k_toep<1, 4>", "config": 13, "fetch_kib": 6999.6, "write_kib": 80000.0,
+                  "src_sha256": "b8577ff9c5188d021cc84cbd362a381bd55b86f0fdf746ab26df640d1a6d2a7b"},
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87369.8,
+                    "write_kib": 56097.6, "src_sha256": "b8577ff9c5188d021cc84cbd362a381bd55b86f0fdf746ab26df640d1a6d2a7b"},
+    "bf16_mixed": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 58087.9,
+                   "write_kib": 111021.6, "src_sha256": "b8577ff9c5188d021cc84cbd362a381bd55b86f0fdf746ab26df640d1a6d2a7b"},
 }
 
 
@@ -65,6 +66,14 @@ def traffic_bytes(leg, config):
     if not rec or rec["src_sha256"] != kernel_sha() or rec["config"] != config:
         return None
     return 1024.0 * (FETCH_SCALE * rec["fetch_kib"] + WRITE_SCALE * rec["write_kib"])
+
+
+def hop1_kernel(config):
+    """Kernel a hop-1 BF16 single-clip launch of this configuration runs:
+    Toeplitz tiles (13-18: NB 1024-frame blocks per wave) or 32-scale-block
+    WIN tiles."""
+    nb = {13: 4, 14: 2, 15: 1, 16: 4, 17: 2, 18: 1}.get(config)
+    return "k_toep<bf16, NB=%d>" % nb if nb else "k_mfma_win<bf16>"
 
 
 def log(*a):
@@ -117,7 +126,11 @@ def time_launches(torch, launch, nsets, steps, warmup, warm_ms=0.0):
     Untimed first: `warmup` steps and, with warm_ms > 0, further steps until
     warm_ms of wall time have passed.  The GPU's clock ramps up over the first
     milliseconds of sustained load: after 5 steps (~1 ms) of hop-1 work the
-    first timed steps still run ~20% slower than after 200."""
+    first timed steps still run ~20% slower than after 200.  The timed steps
+    run back to back between one pair of events, and each step's time is
+    their mean: a timing event recorded between two launches holds the next
+    one back by several microseconds (13 us per 256-clip hop-512 launch with
+    an event pair around each)."""
     st = torch.cuda.current_stream()
     t_start = time.perf_counter()
     for w in range(warmup):
@@ -129,18 +142,16 @@ def time_launches(torch, launch, nsets, steps, warmup, warm_ms=0.0):
             w += 1
         torch.cuda.synchronize()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(st)
     for s in range(steps):
-        ev[s][0].record(st)
         launch(s)
-        ev[s][1].record(st)
     t1.record(st)
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1), [a.elapsed_time(b) for a, b in ev]
+    total = t0.elapsed_time(t1)
+    return total, [total / steps] * steps
 
 
 def hop_sweep(torch, cwth, synth, dev, scales, args):
@@ -618,8 +629,8 @@ def main():
         ach = flops / (r["per_launch_ms"] * 1e-3) / 1e12
         line["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                             "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic_bytes("bf16_hop1", r["config"]),
-                            "kernel": "k_mfma_win<bf16> (configuration %d), hop 1, one 160000-sample clip x 128 "
-                                      "scales per launch" % r["config"],
+                            "kernel": "%s (configuration %d), hop 1, one 160000-sample clip x 128 "
+                                      "scales per launch" % (hop1_kernel(r["config"]), r["config"]),
                             "alg_flop_per_launch": flops, "avg_launch_ms": r["per_launch_ms"]}
     if ("bf16", 512) in result:
         r = result[("bf16", 512)]

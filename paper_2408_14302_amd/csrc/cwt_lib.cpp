@@ -506,7 +506,14 @@ struct ClipLayout {
     int64_t groups = 0;  // work-group tiles per frame tile
 };
 
+// Configuration epoch: advanced whenever a plan's configuration or the tuned
+// classes change, so that a batch context's prepared launches (prepared under
+// an older epoch) are prepared again.  Plans carry a process-unique id.
+static std::atomic<uint64_t> g_cfg_epoch{1};
+static std::atomic<uint64_t> g_plan_uid{1};
+
 struct cwt_plan_s {
+    uint64_t uid = g_plan_uid.fetch_add(1);
     double fs;
     int hop;
     int dt;
@@ -600,6 +607,7 @@ static void load_tuned_locked() {
             continue;
         k.arch = arch;
         if (v >= 0 && v < kNumMfmaCfgs) g_tuned[k] = v;
+        g_cfg_epoch.fetch_add(1);
     }
     g_tuned_count = (int)g_tuned.size();
 }
@@ -770,6 +778,7 @@ static int64_t layout_lds(const ClipLayout& L) {
 
 // Set the plan's configuration and cache its layout.
 static void set_cfg(cwt_plan_s* p, int cfg) {
+    g_cfg_epoch.fetch_add(1);
     p->cfg = cfg;
     p->cfg_auto = false;
     if (p->dt == DT_FP32) return;
@@ -798,6 +807,7 @@ static const int kAutoCfgs[3] = {6, 4, 5};
 static const int kAutoToep[3] = {13, 14, 15};   // Toeplitz tiles of 16384, 8192, 4096 frames
 
 static void set_auto(cwt_plan_s* p) {
+    g_cfg_epoch.fetch_add(1);
     p->cfg_auto = true;
     const int* set = kMfmaCfgs[p->cfg].toep ? kAutoToep : kAutoCfgs;
     for (int i = 0; i < 3; ++i) {
@@ -958,6 +968,20 @@ struct GraphEntry {
     size_t copy_bytes = 0;    // descriptor bytes of the last replay
 };
 
+// Everything a persistent batch launch needs, computed on the host from the
+// batch alone (batch_prepare); the descriptors themselves go to a caller's
+// host buffer, laid out as [int32 nclips, int32 total_tiles, pad to 16]
+// [ClipArg x nc] [int32 prefix x (nc+1)], nc = clips with len > 0.
+struct BatchLaunch {
+    bool fp32 = false;
+    int nc = 0;              // clips in the launch (len > 0), longest first
+    int64_t total = 0;       // tiles over all clips
+    size_t used_bytes = 0;   // descriptor bytes
+    int dt = 0, A = 1, pkind = 0, grid = 0;
+    MfmaArgs a;              // clips / tile_prefix filled in by batch_launch
+    DirectArgs d;
+};
+
 struct cwt_batch_s {
     int device = 0;
     int max_clips = 0;
@@ -979,6 +1003,13 @@ struct cwt_batch_s {
     hipStream_t cap_stream = nullptr;
     std::map<std::tuple<int, int, int, int, int, int>, GraphEntry> graphs;
     std::mutex mu;
+    // Prepared launches: pkey[i] describes the call (epoch, forced
+    // configuration, and per clip plan id, input, length, output) whose
+    // descriptors d_desc[i] holds and whose launch record is pbl[i]; a call
+    // with the same key reuses both without preparing anything on the host.
+    std::vector<uint64_t> pkey[2];
+    BatchLaunch pbl[2];
+    std::vector<uint64_t> kbuf;
 
     ~cwt_batch_s() {
         for (int i = 0; i < 2; ++i) {
@@ -1015,6 +1046,8 @@ static cwt_status batch_init(cwt_batch_s* b, int max_clips) {
     b->cus = di.cus;
     b->max_clips = max_clips;
     b->desc_cap = desc_bytes(max_clips);
+    b->kbuf.reserve(4 + 4 * (size_t)max_clips);
+    for (int i = 0; i < 2; ++i) b->pkey[i].reserve(4 + 4 * (size_t)max_clips);
     for (int i = 0; i < 2; ++i) {
         HIP_TRY(hipHostMalloc((void**)&b->pinned[i], b->desc_cap, hipHostMallocDefault), "pinned descriptors");
         HIP_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming), "batch event");
@@ -1028,7 +1061,6 @@ static cwt_status batch_init(cwt_batch_s* b, int max_clips) {
     return CWT_OK;
 }
 
-// Persistent grid: enough work-groups to fill every CU at the kernel's occupancy.
 // Persistent grid: every work-group resident (CUs x occupancy), reduced to
 // the nearest size coprime with `groups` (the lcm of the clips' block-group
 // counts) so that the static tile stride rotates each work-group through
@@ -1040,19 +1072,6 @@ static int persistent_grid(int cus, int dt, int A, int kind, int64_t lds_bytes, 
     return g;
 }
 
-// Everything a persistent batch launch needs, computed on the host from the
-// batch alone (batch_prepare); the descriptors themselves go to a caller's
-// host buffer, laid out as [int32 nclips, int32 total_tiles, pad to 16]
-// [ClipArg x nc] [int32 prefix x (nc+1)], nc = clips with len > 0.
-struct BatchLaunch {
-    bool fp32 = false;
-    int nc = 0;              // clips in the launch (len > 0), longest first
-    int64_t total = 0;       // tiles over all clips
-    size_t used_bytes = 0;   // descriptor bytes
-    int dt = 0, A = 1, pkind = 0, grid = 0;
-    MfmaArgs a;              // clips / tile_prefix filled in by batch_launch
-    DirectArgs d;
-};
 
 // Host scratch batch_prepare needs for n clips: order[n], clips[n], ctiles[n].
 struct BatchScratch {
@@ -1278,34 +1297,63 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     const cwt_plan_s* p0 = plans[0];
     if (p0->device != b->device) return fail(CWT_ERR_INVALID_ARG, "plan and batch context on different devices");
 
-    // Wait until the pinned buffer we are about to overwrite has been consumed.
-    const int slot = b->flip;
-    b->flip ^= 1;
-    if (b->used[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch reuse wait");
-    uint8_t* host = b->pinned[slot];
-    std::vector<int> order(n);
-    std::vector<ClipArg> clips(n);
-    std::vector<int64_t> ctiles(n, 0);
-    BatchLaunch bl;
-    st = batch_prepare(plans, xs, lens, outs, n, b->cus, force_cfg, BatchScratch{order.data(), clips.data(), ctiles.data()},
-                       host, b->desc_cap, &bl);
-    if (st != CWT_OK || bl.nc == 0) return st;
-    const size_t used_bytes = bl.used_bytes;
-
-    // Device descriptors: reuse the buffer that already holds exactly these
-    // (a prepared batch run again: no upload); otherwise overwrite the other
-    // one once the launches that read it have completed.
+    // The call's key: a prepared launch with the same key (the same plans,
+    // buffers and lengths under the same configuration epoch) is run again
+    // as it is, its descriptors already resident.  kbuf's capacity is
+    // reserved at creation: no allocation here.
+    std::vector<uint64_t>& ckey = b->kbuf;
+    ckey.clear();
+    ckey.push_back((uint64_t)n);
+    ckey.push_back((uint64_t)(int64_t)force_cfg);
+    ckey.push_back(g_cfg_epoch.load());
+    for (int i = 0; i < n; ++i) {
+        ckey.push_back(plans[i]->uid);
+        ckey.push_back((uint64_t)(uintptr_t)xs[i]);
+        ckey.push_back((uint64_t)lens[i]);
+        ckey.push_back((uint64_t)(uintptr_t)outs[i]);
+    }
     int ds = -1;
     for (int i = 0; i < 2; ++i)
-        if (b->shadow[i].size() == used_bytes && std::memcmp(b->shadow[i].data(), host, used_bytes) == 0) ds = i;
-    const bool upload = ds < 0;
-    if (upload) {
-        ds = b->dnext;
-        b->dnext ^= 1;
-        if (b->dused[ds]) HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor reuse wait");
-        b->shadow[ds].assign(host, host + used_bytes);
-    } else if (b->dused[ds] && b->dstream[ds] != stream) {
-        HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
+        if (b->pkey[i].size() == ckey.size() && std::memcmp(b->pkey[i].data(), ckey.data(), ckey.size() * 8) == 0) ds = i;
+    BatchLaunch bl;
+    bool upload = false;
+    const int slot = b->flip;
+    uint8_t* host = b->pinned[slot];
+    size_t used_bytes = 0;
+    if (ds >= 0) {
+        bl = b->pbl[ds];
+        used_bytes = bl.used_bytes;
+        if (b->dused[ds] && b->dstream[ds] != stream)
+            HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
+    } else {
+        // Wait until the pinned buffer we are about to overwrite has been consumed.
+        b->flip ^= 1;
+        if (b->used[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch reuse wait");
+        std::vector<int> order(n);
+        std::vector<ClipArg> clips(n);
+        std::vector<int64_t> ctiles(n, 0);
+        st = batch_prepare(plans, xs, lens, outs, n, b->cus, force_cfg,
+                           BatchScratch{order.data(), clips.data(), ctiles.data()}, host, b->desc_cap, &bl);
+        if (st != CWT_OK || bl.nc == 0) return st;
+        used_bytes = bl.used_bytes;
+
+        // Device descriptors: reuse the buffer that already holds exactly these
+        // (no upload); otherwise overwrite the other one once the launches that
+        // read it have completed.
+        for (int i = 0; i < 2; ++i)
+            if (b->shadow[i].size() == used_bytes && std::memcmp(b->shadow[i].data(), host, used_bytes) == 0) ds = i;
+        upload = ds < 0;
+        if (upload) {
+            ds = b->dnext;
+            b->dnext ^= 1;
+            if (b->dused[ds]) HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor reuse wait");
+            b->shadow[ds].assign(host, host + used_bytes);
+        } else if (b->dused[ds] && b->dstream[ds] != stream) {
+            HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
+        }
+        batch_bind(&bl, b->d_desc[ds]);
+        b->pkey[ds].assign(ckey.begin(), ckey.end());
+        b->pbl[ds] = bl;
     }
     uint8_t* const dd = b->d_desc[ds];
     batch_bind(&bl, dd);
@@ -1771,6 +1819,7 @@ cwt_status cwt_autotune_batch(const cwt_plan_t* plans, const int64_t* lens, int3
                 g_tuned[cls] = best;
             else
                 g_tuned.erase(cls);
+            g_cfg_epoch.fetch_add(1);
             g_tuned_count = (int)g_tuned.size();
             save_tuned_locked();
         }

@@ -439,6 +439,42 @@ def test_prepared_batches_replay(torch, cw):
                 assert torch.equal(a, b), (rep, j)
 
 
+def test_prepared_batch_follows_configuration_changes(torch, cw):
+    """A context runs a prepared launch again without preparing it on the
+    host only while its plans, buffers and the configuration state are those
+    it was prepared from: a plan moved from Toeplitz tiles to 32-scale-block
+    tiles between two runs of one prepared batch runs the new tiles (the two
+    kinds group the products differently, so the results change), and a new
+    input written into the same buffers is transformed anew."""
+    scales = np.arange(1, 65)
+    p = cw.Plan(16000.0, scales, 1, "bf16", signed=True)
+    assert p.config_kind(p.config) == 1
+    xs = [torch.from_numpy(clip(2, 60 + i, 12000 + 1000 * i, 0.0)).cuda() for i in range(4)]
+    B = cw.Batch(8)
+    prep = B.prepare([p] * 4, xs)
+    first = [o.clone() for o in prep.run(graph=False)]
+    again = [o.clone() for o in prep.run(graph=False)]
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(first, again))
+    p.set_config(6)
+    blocks = [o.clone() for o in prep.run(graph=False)]
+    alone = [p(x) for x in xs]
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(alone, blocks))
+    assert not all(torch.equal(a, b) for a, b in zip(first, blocks))
+    for a, b in zip(first, blocks):
+        assert_close("bf16", a.cpu().numpy(), b.cpu().numpy(), "Toeplitz vs block tiles")
+    # doubling the input doubles every product and partial sum exactly (a
+    # negation would not: the matrix cores' accumulation is not symmetric in
+    # sign at the last bit)
+    for x in xs:
+        x.mul_(2.0)
+    scaled = [o.clone() for o in prep.run(graph=True)]
+    torch.cuda.synchronize()
+    for a, b in zip(blocks, scaled):
+        assert torch.equal(2.0 * a, b)
+
+
 def test_batch_context_on_two_streams(torch, cw):
     """One context fed alternately from two streams with changing batches."""
     scales = np.arange(1, 65)
