@@ -999,6 +999,11 @@ struct cwt_batch_s {
     hipEvent_t ddone[2] = {nullptr, nullptr};
     hipStream_t dstream[2] = {nullptr, nullptr};
     bool dused[2] = {false, false};
+    // launches reading d_desc[i] queued on dstream[i] since ddone[i] was last
+    // recorded: the event is recorded only when something has to wait for
+    // them (an upload into the buffer, a launch from another stream), since
+    // an event marker between two launches holds the second one back
+    bool dpending[2] = {false, false};
     int dnext = 0;
     hipStream_t cap_stream = nullptr;
     std::map<std::tuple<int, int, int, int, int, int>, GraphEntry> graphs;
@@ -1023,6 +1028,8 @@ struct cwt_batch_s {
             if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
             if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
         }
+        // launches still reading the descriptors (their stream may be gone)
+        if (dpending[0] || dpending[1]) (void)hipDeviceSynchronize();
         for (int i = 0; i < 2; ++i) {
             if (ddone[i]) {
                 (void)hipEventSynchronize(ddone[i]);
@@ -1286,6 +1293,18 @@ static hipError_t batch_launch(const BatchLaunch& bl, const uint8_t* dd, hipStre
     return launch_mfma(bl.dt, bl.A, 1, bl.a, bl.pkind, bl.grid, stream);
 }
 
+// Make `stream` wait for the launches that read descriptor buffer ds
+// (recording their event first if it is pending).
+static hipError_t wait_desc(cwt_batch_s* b, int ds, hipStream_t stream) {
+    if (!b->dused[ds]) return hipSuccess;
+    if (b->dpending[ds]) {
+        hipError_t e = hipEventRecord(b->ddone[ds], b->dstream[ds]);
+        if (e != hipSuccess) return e;
+        b->dpending[ds] = false;
+    }
+    return hipStreamWaitEvent(stream, b->ddone[ds], 0);
+}
+
 static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float* const* xs,
                             const int64_t* lens, float* const* outs, int32_t n, int use_graph,
                             hipStream_t stream, int force_cfg = -1) {
@@ -1323,8 +1342,7 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     if (ds >= 0) {
         bl = b->pbl[ds];
         used_bytes = bl.used_bytes;
-        if (b->dused[ds] && b->dstream[ds] != stream)
-            HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
+        if (b->dused[ds] && b->dstream[ds] != stream) HIP_TRY(wait_desc(b, ds, stream), "descriptor upload wait");
     } else {
         // Wait until the pinned buffer we are about to overwrite has been consumed.
         b->flip ^= 1;
@@ -1346,10 +1364,10 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
         if (upload) {
             ds = b->dnext;
             b->dnext ^= 1;
-            if (b->dused[ds]) HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor reuse wait");
+            HIP_TRY(wait_desc(b, ds, stream), "descriptor reuse wait");
             b->shadow[ds].assign(host, host + used_bytes);
         } else if (b->dused[ds] && b->dstream[ds] != stream) {
-            HIP_TRY(hipStreamWaitEvent(stream, b->ddone[ds], 0), "descriptor upload wait");
+            HIP_TRY(wait_desc(b, ds, stream), "descriptor upload wait");
         }
         batch_bind(&bl, b->d_desc[ds]);
         b->pkey[ds].assign(ckey.begin(), ckey.end());
@@ -1358,11 +1376,13 @@ static cwt_status batch_run(cwt_batch_s* b, const cwt_plan_t* plans, const float
     uint8_t* const dd = b->d_desc[ds];
     batch_bind(&bl, dd);
     auto finish = [&]() -> cwt_status {
-        HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
-        HIP_TRY(hipEventRecord(b->ddone[ds], stream), "descriptor event");
-        b->used[slot] = true;
+        if (upload) {   // the copy reads the pinned buffer: its next writer waits for this
+            HIP_TRY(hipEventRecord(b->done[slot], stream), "batch event");
+            b->used[slot] = true;
+        }
         b->dused[ds] = true;
         b->dstream[ds] = stream;
+        b->dpending[ds] = true;
         return CWT_OK;
     };
 
