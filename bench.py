@@ -400,17 +400,21 @@ def error_report(torch, cwth, synth, dev, args):
     geometric scales (hops 128, 512; BF16, FP8, BF16x3 and FP32).  Every
     coefficient is compared (the oracle runs on all host threads)."""
     import oracle
-    tol = {"fp32": (1e-5, 1e-4), "fp16": (2e-3, 2e-3), "bf16": (1e-2, 1e-2), "bf16x3": (5e-5, 5e-5),
-           "fp8": (1.5e-1, 2e-1)}
+    # the bounds the parity tests assert; FP8's per workload (its error grows
+    # with the dynamic range the transform spans: the widest scales' output
+    # against the narrowest ones' quantisation)
+    tol = {"fp32": (1e-5, 1e-4), "fp16": (2e-3, 2e-3), "bf16": (1e-2, 1e-2), "bf16x3": (5e-5, 5e-5)}
     work = [("1 s at 16 kHz, 32 linear scales, SNR 0 dB", 16000, 16000.0, synth.linear_scales(32),
-             [synth.make_clip(synth.clip_seed(1, 0), 16000, 16000.0, 0.0)], (1, 64), tuple(tol)),
+             [synth.make_clip(synth.clip_seed(1, 0), 16000, 16000.0, 0.0)], (1, 64), tuple(tol) + ("fp8",),
+             (2.5e-2, 0.12)),
             ("10 s at 16 kHz, 128 linear scales, SNR -6/0/6 dB", N, FS, synth.linear_scales(128),
              [synth.make_clip(synth.clip_seed(2, i), N, FS, snr) for i, snr in enumerate((-6.0, 0.0, 6.0))],
-             (1, 32, 128, 256, 512), tuple(tol)),
+             (1, 32, 128, 256, 512), tuple(tol) + ("fp8",), (2.5e-2, 0.15)),
             ("8 x 60 s at 48 kHz, 256 geometric scales 1..1024", 2880000, 48000.0, synth.geometric_scales(256, 1024.0),
              [synth.make_clip(synth.clip_seed(5, c), 2880000, 48000.0, 0.0) for c in range(8)], (128, 512),
-             ("bf16", "fp8", "bf16x3", "fp32"))]
-    for name, n, fs, scales, clips, hops, dts in work:
+             ("bf16", "fp8", "bf16x3", "fp32"), (2.5e-2, 0.2))]
+    for name, n, fs, scales, clips, hops, dts, fp8_tol in work:
+        tol["fp8"] = fp8_tol
         xs = [torch.from_numpy(c).to(dev) for c in clips]
         for hop in hops:
             t0 = time.perf_counter()

@@ -17,10 +17,21 @@ constexpr int kWaveSize = 64;
 constexpr int kMfmaWaves = 4;      // waves per MFMA work-group (split along frames)
 constexpr int kFp8Segment = 128;        // frames per FP8 signal-scale segment (the largest FP8 tile)
 constexpr int kFp8SegmentMaxHop = 128;  // FP8 scales per segment up to this hop, per tile beyond
-constexpr int kDirectWaves = 4;    // waves per direct-sum work-group (64 frames each)
-constexpr int kDirectFrames = 64 * kDirectWaves;  // frames per direct-sum work-group (one per thread)
-constexpr int kDirectRows = 16;    // scales per direct-sum work-group (every wave runs all of them)
-constexpr int kDirectChunk = 32;   // taps staged per LDS chunk in the direct kernel
+// Direct (FP32) work-groups of kDirectWaves waves, in one of two layouts
+// (ClipArg::ws of an FP32 clip): 1 = kDirectFrames frames (one per thread)
+// x one group of kDirectRows scales that every wave runs, staged
+// kDirectChunk taps at a time; kDirectGroups = kDirectWideFrames frames (one
+// per lane) x kDirectGroups groups, one per wave, staged kDirectWideChunk
+// taps at a time (each staged value then feeds 64 scales: the layout for
+// large hops, whose frames share few samples).
+constexpr int kDirectWaves = 4;
+constexpr int kDirectFrames = 64 * kDirectWaves;
+constexpr int kDirectRows = 16;
+constexpr int kDirectChunk = 32;
+constexpr int kDirectGroups = kDirectWaves;
+constexpr int kDirectWideFrames = 64;
+constexpr int kDirectWideChunk = 128;
+constexpr int kDirectWideHop = 256;   // layout kDirectGroups from this hop on
 
 // K (taps) consumed by one MFMA for the operand type.
 __host__ __device__ constexpr int kstep_of(int dt) { return dt == DT_FP8 ? 64 : 16; }
@@ -98,7 +109,8 @@ struct ClipArg {
     int32_t swz;     // XOR-swizzle shift (linear and window modes), -1 for none
     int32_t wb;      // window mode: 32-scale blocks per work-group (1, 2 or 4)
     int32_t cso;     // linear and window modes with copies > 1: copy stride = units + cso (16-byte units)
-    int32_t ws;      // window mode: waves sharing one frame group (their blocks split WS ways)
+    int32_t ws;      // window mode: waves sharing one frame group (their blocks split WS ways);
+                     // FP32 clips: scale groups per work-group (1 or kDirectGroups)
 };
 
 // LINEAR: chunked linear window, one block per tile; ROWS: chunked per-frame

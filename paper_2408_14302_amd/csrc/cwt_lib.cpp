@@ -883,8 +883,13 @@ static ClipArg make_clip(const cwt_plan_s* p, const float* x, int64_t len, float
     c.wb = 1;
     c.ws = 1;
     if (p->dt == DT_FP32) {
-        c.ntile = (int32_t)((c.K + kDirectFrames - 1) / kDirectFrames);
-        if (tiles_out) *tiles_out = (int64_t)c.ntile * (int64_t)p->bank->dgroups.size();
+        // four scale groups per work-group from hop kDirectWideHop on (see direct.hip)
+        const bool wide = p->hop >= kDirectWideHop;
+        const int64_t ng = (int64_t)p->bank->dgroups.size();
+        c.ws = wide ? kDirectGroups : 1;
+        const int F = wide ? kDirectWideFrames : kDirectFrames;
+        c.ntile = (int32_t)((c.K + F - 1) / F);
+        if (tiles_out) *tiles_out = (int64_t)c.ntile * (wide ? (ng + kDirectGroups - 1) / kDirectGroups : ng);
         return c;
     }
     const bool cached = cached_ok && (p->lay.s.mode != STAGE_LINEAR || chunk == p->lay_chunk);
