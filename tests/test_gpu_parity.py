@@ -475,6 +475,32 @@ def test_prepared_batch_follows_configuration_changes(torch, cw):
         assert torch.equal(2.0 * a, b)
 
 
+def test_prepared_batch_from_two_streams(torch, cw):
+    """A prepared batch run again from a second stream: the run reuses the
+    resident descriptors, and the launches that last read them on the first
+    stream are waited for before any later upload overwrites them."""
+    scales = np.arange(1, 65)
+    plans = {h: cw.Plan(16000.0, scales, h, "bf16") for h in (1, 256, 512)}
+    B = cw.Batch(16)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sets = []
+    for seed in (51, 52):
+        xs, hs = _batch_inputs(torch, seed, 10, [1, 256, 512], lo=4000, hi=40000)
+        pl = [plans[h] for h in hs]
+        sets.append(([p(x) for p, x in zip(pl, xs)], B.prepare(pl, xs)))
+    torch.cuda.synchronize()
+    for rep in range(6):
+        alone, prep = sets[rep % 2 if rep < 4 else 0]
+        st = streams[(rep // 2) % 2]
+        with torch.cuda.stream(st):
+            for o in prep.outs:
+                o.fill_(-1.0)
+            outs = prep.run(stream=st, graph=bool(rep % 3 == 2))
+        st.synchronize()
+        for a, b in zip(alone, outs):
+            assert torch.equal(a, b), rep
+
+
 def test_batch_context_on_two_streams(torch, cw):
     """One context fed alternately from two streams with changing batches."""
     scales = np.arange(1, 65)
