@@ -45,12 +45,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_toep<1, 4>", "config": 13, "fetch_kib": 6999.6, "write_kib": 80000.0,
-                  "src_sha256": "b8577ff9c5188d021cc84cbd362a381bd55b86f0fdf746ab26df640d1a6d2a7b"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87369.8,
-                    "write_kib": 56097.6, "src_sha256": "b8577ff9c5188d021cc84cbd362a381bd55b86f0fdf746ab26df640d1a6d2a7b"},
-    "bf16_mixed": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 58050.2,
-                   "write_kib": 110469.6, "src_sha256": "b8577ff9c5188d021cc84cbd362a381bd55b86f0fdf746ab26df640d1a6d2a7b"},
+    "bf16_hop1": {"kernel": "k_toep_batch<1>", "config": 13, "fetch_kib": 12031.3, "write_kib": 240034.9,
+                  "src_sha256": "4450bb5e4cf9037743088f821a0cb8ed594d88439734be7e1f5eaf64ac1d8788"},
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87355.1,
+                    "write_kib": 56100.8, "src_sha256": "4450bb5e4cf9037743088f821a0cb8ed594d88439734be7e1f5eaf64ac1d8788"},
+    "bf16_mixed": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 58071.2,
+                   "write_kib": 110479.4, "src_sha256": "4450bb5e4cf9037743088f821a0cb8ed594d88439734be7e1f5eaf64ac1d8788"},
 }
 
 
@@ -70,11 +70,10 @@ def traffic_bytes(leg, config):
 
 
 def hop1_kernel(config):
-    """Kernel a hop-1 BF16 single-clip launch of this configuration runs:
-    Toeplitz tiles (13-18: NB 1024-frame blocks per wave) or 32-scale-block
-    WIN tiles."""
-    nb = {13: 4, 14: 2, 15: 1, 16: 4, 17: 2, 18: 1}.get(config)
-    return "k_toep<bf16, NB=%d>" % nb if nb else "k_mfma_win<bf16>"
+    """Kernel a hop-1 BF16 batch of several clips of this configuration runs:
+    Toeplitz tiles in one grid over the clips (configuration 13, 4 x 4096
+    frames per work-group) or 32-scale-block tiles in the persistent kernel."""
+    return "k_toep_batch<bf16>" if config == 13 else "k_mfma_persistent<bf16>"
 
 
 def log(*a):
@@ -514,19 +513,21 @@ def main():
     stream = torch.cuda.current_stream()
 
     def leg_hop1(dt):
+        """The three clips of a step in one launch of the prepared batch (for
+        BF16 one grid of Toeplitz tiles over the three clips, k_toep_batch;
+        for FP32 the flat direct-sum grid), outputs rotated over two sets."""
         plan = cwth.Plan(FS, scales, 1, dt)
+        B = cwth.Batch(len(clips))
+        prep = [B.prepare([plan] * len(clips), clips, out1[j]) for j in range(2)]
+
         def launch(s):
-            o = out1[s % 2]
-            for c, x in enumerate(clips):
-                plan.execute(x, o[c], stream)
+            prep[s % 2].run(stream=stream.cuda_stream, graph=False)
         steps = args.steps if dt == "bf16" else max(5, args.steps // 5)
         total, per = time_launches(torch, launch, 2, steps, args.warmup)
         ms = total / steps
         coeffs = len(clips) * S * K1
-        # per-kernel duration: one launch per clip inside each step
-        per_launch_ms = float(np.mean(per)) / len(clips)
-        return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": per_launch_ms,
-                "steps": steps, "config": plan.launch_config(N, 1)}
+        return {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3), "per_launch_ms": float(np.mean(per)),
+                "clips_per_launch": len(clips), "steps": steps, "config": plan.launch_config(N, len(clips))}
 
     # hop 512: many clips per launch (one clip alone is ~0.1 us of work)
     nb = args.batch512
@@ -636,11 +637,11 @@ def main():
     # ---------------- roofline of the dominant kernel ----------------
     if ("bf16", 1) in result:
         r = result[("bf16", 1)]
-        flops = flops_per_frame * K1                      # one launch = one clip
+        flops = flops_per_frame * K1 * len(clips)         # one launch = the step's three clips
         ach = flops / (r["per_launch_ms"] * 1e-3) / 1e12
         line["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                             "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic_bytes("bf16_hop1", r["config"]),
-                            "kernel": "%s (configuration %d), hop 1, one 160000-sample clip x 128 "
+                            "kernel": "%s (configuration %d tiles), hop 1, three 160000-sample clips x 128 "
                                       "scales per launch" % (hop1_kernel(r["config"]), r["config"]),
                             "alg_flop_per_launch": flops, "avg_launch_ms": r["per_launch_ms"]}
     if ("bf16", 512) in result:

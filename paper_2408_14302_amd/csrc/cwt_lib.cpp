@@ -1194,13 +1194,19 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     bl->fp32 = fp32;
     bl->nc = nc;
     if (nc == 0) return CWT_OK;
+    // A batch of Toeplitz clips only runs them in one grid of their
+    // single-clip tiles (k_toep_batch); Toeplitz clips among others run in
+    // the every-layout persistent kernel with kToepBatchNB blocks per wave.
+    bool toep_only = !fp32;
+    for (int j = 0; j < nc; ++j) toep_only = toep_only && plan_toep(plans[sc.order[j]]);
+    const MfmaCfg& ct = kMfmaCfgs[toep_only ? kToepCfg0 : kToepBatchCfg];
     // Longest first (most tiles first) so the persistent grid drains evenly.
     int64_t maxbuf = 16, maxraw = 0, maxwin = 0;
     for (int j = 0; j < nc; ++j) {
         const int i = sc.order[j];
         ClipLayout L;
         const bool tp = plan_toep(plans[i]);
-        sc.clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], tp ? kMfmaCfgs[kToepBatchCfg] : c,
+        sc.clips[i] = make_clip(plans[i], xs[i], lens[i], outs[i], tp ? ct : c,
                                 !tp && cached_ok && plans[i]->cfg == cfg, chunk, &L, &sc.ctiles[i]);
         if (fp32) continue;
         if (L.s.mode == STAGE_WIN || L.s.mode == STAGE_TOEP) {
@@ -1267,6 +1273,11 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
         a.ntgroups = (int)bk.tgroups.size();
         a.toep_bg = kMfmaCfgs[kToepBatchCfg].wb;
     }
+    if (toep_only) {
+        bl->pkind = 4;
+        bl->grid = (int)total;
+        return CWT_OK;
+    }
     // WIN-only batches run the kernel compiled for the WIN register budget.
     bool win_only = true;
     for (int j = 0; j < nc; ++j) win_only = win_only && hc[j].mode == STAGE_WIN;
@@ -1295,6 +1306,7 @@ static hipError_t batch_launch(const BatchLaunch& bl, const uint8_t* dd, hipStre
     if (bl.fp32)
         return launch_direct_batch(bl.d, (const ClipArg*)(dd + 16), (const int32_t*)(dd + 16 + sizeof(ClipArg) * bl.nc),
                                    bl.nc, (int)bl.total, stream);
+    if (bl.pkind == 4) return launch_toep_batch(bl.dt, bl.a, bl.grid, stream);
     return launch_mfma(bl.dt, bl.A, 1, bl.a, bl.pkind, bl.grid, stream);
 }
 
@@ -1688,7 +1700,7 @@ int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips) {
     if (!plan || len < 1 || n_clips < 1) return -1;
     if (plan->dt == DT_FP32) return plan->cfg;
     const int64_t K = (len + plan->hop - 1) / plan->hop;
-    if (n_clips > 1 && plan_toep(plan)) return kToepBatchCfg;   // batches run one Toeplitz tile size
+    if (n_clips > 1 && plan_toep(plan)) return kToepCfg0;   // batches of Toeplitz clips: one grid of its tiles
     const int cfg = auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups * n_clips; });
     std::vector<cwt_plan_t> pl(n_clips, plan);
     std::vector<int64_t> ln(n_clips, len);

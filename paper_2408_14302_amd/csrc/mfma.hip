@@ -1295,6 +1295,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     process_tile_toep<DT, NB, kToepPrefetch>(a, a.clip, tile, g0, g1, lds);
 }
 
+// Toeplitz tiles of a batch of hop-1 clips in one grid.  The frame tiles of
+// all clips form one sequence (clip c's start at tile_prefix[c] / ntgroups)
+// and work-group ids map to (group, tile) as for one clip over that
+// sequence: the widest groups first across all clips, each XCD one group in
+// eight.  One launch then pays one tail for all its clips, where separate
+// launches each wait for their own widest groups' last work items.
+template <int DT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_toep_batch(MfmaArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int ntg = a.ntgroups;
+    int g0, g1, t;
+    toep_unit(blockIdx.x, ntg, 1, a.total_tiles / ntg, &g0, &g1, &t);
+    int lo = 0, hi = a.nclips - 1;   // last clip c with tile_prefix[c] / ntg <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tile_prefix[mid] / ntg <= t) lo = mid; else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const ClipArg c = a.clips[lo];
+    process_tile_toep<DT, 4, kToepPrefetch>(a, c, t - a.tile_prefix[lo] / ntg, g0, -1, lds);
+}
+
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
 // (G = gridDim.x, every work-group resident) with no atomics; the host picks G
 // coprime with the number of block groups so that a work-group's tiles rotate
@@ -1455,7 +1477,12 @@ static hipError_t toep_attr() {
 }
 
 hipError_t mfma_init_attributes() {
-    hipError_t e = toep_attr<DT_BF16, 1>();
+    hipError_t e = hipFuncSetAttribute((const void*)k_toep_batch<DT_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       dyn_lds_max());
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_toep_batch<DT_FP16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                dyn_lds_max());
+    if (e == hipSuccess) e = toep_attr<DT_BF16, 1>();
     if (e == hipSuccess) e = toep_attr<DT_BF16, 2>();
     if (e == hipSuccess) e = toep_attr<DT_BF16, 4>();
     if (e == hipSuccess) e = toep_attr<DT_FP16, 1>();
@@ -1507,6 +1534,18 @@ static hipError_t launch_toep1(int NB, const MfmaArgs& a, int grid, hipStream_t 
         case 4: return launch_toep2<DT, 4>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_toep_batch(int dt, const MfmaArgs& a, int grid, hipStream_t s) {
+    if ((size_t)a.shm_bytes > (size_t)dyn_lds_max() || grid <= 0 || a.ntgroups <= 0) return hipErrorInvalidValue;
+    (void)hipGetLastError();
+    if (dt == DT_BF16)
+        hipLaunchKernelGGL((k_toep_batch<DT_BF16>), dim3(grid), dim3(256), (size_t)a.shm_bytes, s, a);
+    else if (dt == DT_FP16)
+        hipLaunchKernelGGL((k_toep_batch<DT_FP16>), dim3(grid), dim3(256), (size_t)a.shm_bytes, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_toep(int dt, int NB, const MfmaArgs& a, int grid, hipStream_t s) {

@@ -439,6 +439,32 @@ def test_prepared_batches_replay(torch, cw):
                 assert torch.equal(a, b), (rep, j)
 
 
+@pytest.mark.parametrize("dt", ["bf16", "fp16"])
+def test_batch_of_hop1_clips_in_one_toeplitz_grid(torch, cw, dt):
+    """A batch of hop-1 clips only runs their single-clip Toeplitz tiles in
+    one grid (the frame tiles of all clips in one sequence): bit-identical to
+    the clips launched alone, directly and as graph replays, for clips
+    shorter than one tile, spanning many, and empty; the same batch among a
+    hop-256 clip runs the persistent kernel, with the same bits too."""
+    scales = np.arange(1, 97)
+    p = cw.Plan(16000.0, scales, 1, dt, signed=True)
+    p256 = cw.Plan(16000.0, scales, 256, dt, signed=True)
+    lens = [3000, 16384, 16385, 40000, 170000, 90001, 0, 12345]
+    xs = [torch.from_numpy(clip(2, 70 + i, n, 0.0)).cuda() if n else torch.zeros(0, device="cuda")
+          for i, n in enumerate(lens)]
+    alone = [p(x) for x in xs]
+    outs = cw.execute_batch([p] * len(xs), xs)
+    B = cw.Batch(16)
+    g = B([p] * len(xs), xs, graph=True)
+    g2 = B([p] * len(xs), xs, graph=True)
+    mixed = cw.execute_batch([p] * len(xs) + [p256], xs + [xs[4]])
+    torch.cuda.synchronize()
+    for i, a in enumerate(alone):
+        for b in (outs[i], g[i], g2[i], mixed[i]):
+            assert torch.equal(a, b), (dt, i, lens[i])
+    assert p.launch_config(160000, len(xs)) == 13
+
+
 def test_prepared_batch_follows_configuration_changes(torch, cw):
     """A context runs a prepared launch again without preparing it on the
     host only while its plans, buffers and the configuration state are those
@@ -666,7 +692,7 @@ def test_launch_configuration_follows_the_launch(torch, cw):
     scales = np.arange(1, 129)
     p1 = cw.Plan(16000.0, scales, 1, "bf16")
     assert p1.config_kind(p1.launch_config(160000)) == 1          # hop 1: Toeplitz tiles
-    assert p1.launch_config(160000, 3) == 14                       # the batch tile size
+    assert p1.launch_config(160000, 3) == 13                       # hop-1 batches: one grid of these tiles
     assert cw.Plan(16000.0, scales, 1, "bf16x3").config_kind(6) == 0
     p = cw.Plan(16000.0, scales, 512, "bf16", signed=True)
     assert p.config == 6

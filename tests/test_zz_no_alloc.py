@@ -51,6 +51,27 @@ def test_noalloc_batch_matches_execute_batch_twice(dt):
         print("noalloc %s call %d: %d clips bit-identical to cwt_execute_batch" % (dt, call, len(xs)))
 
 
+def test_noalloc_batch_of_hop1_clips():
+    """A batch of hop-1 clips only (one grid of Toeplitz tiles) through the
+    allocation-free entry point: the bits of cwt_execute_batch."""
+    torch = torch_cuda()
+    from paper_2408_14302_amd import cwth
+    lib = cwth.raw()
+    p = cwth.Plan(16000.0, np.arange(1, 65, dtype=np.float64), 1, "bf16", signed=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    lens = [20000, 4000, 100000, 0, 65000]
+    xs = [torch.from_numpy(synth.make_clip(5000 + i, n, 16000.0, 0.0)).cuda() if n else torch.zeros(0, device="cuda")
+          for i, n in enumerate(lens)]
+    ref = [torch.full((64, p.num_frames(x.numel())), -1.0, device="cuda") for x in xs]
+    got = [torch.full((64, p.num_frames(x.numel())), -2.0, device="cuda") for x in xs]
+    assert _raw_batch(lib, "cwt_execute_batch", [p] * len(xs), xs, ref, stream) == cwth.OK
+    st = _raw_batch(lib, "cwt_execute_batch_noalloc", [p] * len(xs), xs, got, stream)
+    assert st == cwth.OK, lib.cwt_last_error()
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(ref, got)):
+        assert torch.equal(a, b), (i, lens[i])
+
+
 def test_noalloc_rejects_more_than_512_clips():
     torch = torch_cuda()
     from paper_2408_14302_amd import cwth
