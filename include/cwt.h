@@ -112,11 +112,13 @@ cwt_status cwt_execute(cwt_plan_t plan, const float* x, int64_t len, float* out,
                        void* stream);
 
 /*
- * Queue n clips as ONE persistent launch: clip c is transformed with plans[c]
- * (its own hop) from xs[c] (device float32[lens[c]]) into outs[c] (device
- * float32[n_scales * cwt_num_frames(plans[c], lens[c])]).  All plans must share
- * dtype, output mode and scale set (CWT_ERR_UNSUPPORTED otherwise); hops may
- * differ.  Each clip's result is bit-identical to cwt_execute of that clip.
+ * Queue n clips as ONE launch (the persistent batch kernel; a batch of hop-1
+ * Toeplitz clips only runs their tiles in one grid): clip c is transformed
+ * with plans[c] (its own hop) from xs[c] (device float32[lens[c]]) into
+ * outs[c] (device float32[n_scales * cwt_num_frames(plans[c], lens[c])]).  All
+ * plans must share dtype, output mode and scale set (CWT_ERR_UNSUPPORTED
+ * otherwise); hops may differ.  Each clip's result is bit-identical to
+ * cwt_execute of that clip.
  * Uses a library-owned batch context for the calling thread and device and
  * launches directly (no graph); see cwt_batch_create for the explicit form,
  * which can also replay the launch as a captured HIP graph.
@@ -148,7 +150,8 @@ cwt_status cwt_execute_batch_noalloc(const cwt_plan_t* plans, const float* const
  * the persistent launch, or the launch alone) that cwt_batch_execute replays.
  * A batch whose descriptors equal those already held by one of the device
  * buffers (the same plans, buffers and lengths run again) is launched without
- * an upload.  Calls on one context are serialised by a mutex; a call may wait
+ * an upload, and without any host preparation while no plan's configuration
+ * and no tuned class has changed since.  Calls on one context are serialised by a mutex; a call may wait
  * on the host until the pinned buffer it reuses has been consumed (two calls
  * back), and a device buffer is overwritten only after the launches that read
  * it have completed, also when they were queued on another stream.
@@ -213,8 +216,9 @@ int32_t cwt_plan_num_configs(cwt_plan_t plan);
  * FP16 and BF16x3 results are bit-identical across the configurations of one
  * kind (and between a clip alone and in a batch); the two kinds sum each
  * coefficient's products in different groups of 16 and agree within the
- * dtype's tolerance.  A batch runs a Toeplitz plan's clips as Toeplitz tiles
- * (configuration 14). */
+ * dtype's tolerance.  A batch runs a Toeplitz plan's clips as Toeplitz tiles:
+ * configuration 13's in one grid when every clip of the batch is one, else
+ * configuration 14's in the persistent kernel. */
 int32_t cwt_plan_config_kind(cwt_plan_t plan, int32_t index);
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
 
