@@ -140,23 +140,24 @@ __global__ void k_gen_mfma(const double* __restrict__ scales, int nscales,
     }
 }
 
-// Toeplitz bank: one thread per (group, step, scale, lane); the lane's
-// eight taps t[jb + 16 d + 8 (lane / 32) + e - lane % 32], e = 0 .. 7.
+// Toeplitz bank: one thread per (group, scale, unit k, copy r); element i of
+// the unit is t[8 k + i + jb - 24 - r].
 template <int DT>
 __global__ void k_gen_toep(const double* __restrict__ scales, int nscales, const ToepGroup* __restrict__ groups,
                            int ngroups, uint8_t* __restrict__ frags) {
     const int g = blockIdx.y;
     if (g >= ngroups) return;
     const ToepGroup G = groups[g];
-    const int total = G.D * kToepScales * 64;
+    const int CL = toep_copy_units(G.D);
+    const int total = kToepScales * CL * 8;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int lane = i % 64, sc = (i / 64) % kToepScales, d = i / (64 * kToepScales);
+        const int r = i % 8, k = (i / 8) % CL, sc = i / (8 * CL);
         const int pos = g * kToepScales + sc;
         const bool valid = pos < nscales;
         const double s = valid ? scales[pos] : 1.0;
         const int M = valid ? (int)floor(8.0 * s) : -1;
         uint16_t* dst = (uint16_t*)(frags + G.frag_off + (int64_t)i * 16);
-        const int m0 = G.jb + 16 * d + 8 * (lane / 32) - lane % 32;
+        const int m0 = 8 * k + G.jb - 24 - r;
         for (int e = 0; e < 8; ++e) {
             const int m = m0 + e;
             const double t = (m >= -M && m <= M) ? morlet_tap(s, m) : 0.0;

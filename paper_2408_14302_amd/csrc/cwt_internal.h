@@ -66,19 +66,32 @@ struct MfmaBlock {
 };
 
 // Toeplitz bank (BF16/FP16, hop 1): groups of kToepScales consecutive sorted
-// scales.  Group g runs K-steps d = 0 .. D-1 over p = jb + 16 d + u (u < 16)
-// and stores, for every step and scale, one B-operand fragment in lane order:
-// lane l holds t[jb + 16 d + 8 (l / 32) + e - l % 32], e = 0 .. 7 (zero outside
-// the scale's support), 1 KiB per fragment, the group's scales interleaved
-// per step.
+// scales.  Group g runs K-steps d = 0 .. D-1 over p = jb + 16 d + u (u < 16).
+// The B-operand fragment of step d and one scale gives lane l the eight taps
+// t[jb + 16 d + 8 (l / 32) - l % 32 + e], e = 0 .. 7: a Toeplitz block, fixed
+// by 47 consecutive taps, and lane l's run always starts at an index
+// congruent to -(l % 32) mod 8.  The bank therefore holds, per scale, eight
+// shifted copies of the taps: copy r has t[8 k + i + jb - 24 - r] (zero
+// outside the scale's support) at element i < 8 of its 16-byte unit k, so that
+// lane l reads one aligned unit of copy (l % 32) mod 8, unit 2 d + l / 32 -
+// (l % 32) / 8 + 3.  Units k = 0 .. 2 D + 2, stored [scale][k][copy]: the eight
+// copies of a unit are 128 consecutive bytes.
 constexpr int kToepScales = 2;
 constexpr int kToepBatchNB = 2;    // 1024-frame blocks per wave in batch tiles
-constexpr int kToepPrefetch = 8;   // K-steps between a tap fragment's load and its use (single-clip launches)
+// The K loop takes the taps from LDS, kToepChunk steps at a time: units
+// 2 d0 .. 2 d0 + kToepChunkK - 1 of every copy of both scales, two buffers.
+constexpr int kToepChunk = 32;
+constexpr int kToepChunkK = 2 * kToepChunk + 3;
+constexpr int kToepChunkUnits = kToepScales * kToepChunkK * 8;
+constexpr int kToepTapBytes = 2 * kToepChunkUnits * 16;
+__host__ __device__ constexpr int toep_copy_units(int D) { return 2 * D + 3; }
+__host__ __device__ constexpr int64_t toep_group_bytes(int D) { return (int64_t)kToepScales * toep_copy_units(D) * 8 * 16; }
 // First p and K-steps of a group whose widest scale has half-width M, and the
-// LDS window (2-byte operands) of a tile of 4 * 1024 * NB frames over D steps.
+// LDS (2-byte operands, plus the tap buffers) of a tile of 4 * 1024 * NB
+// frames over D steps.
 __host__ __device__ constexpr int toep_jb(int M) { return -8 * ((M + 7) / 8); }
 __host__ __device__ constexpr int toep_steps(int M) { return (((M + 32 - toep_jb(M) + 15) / 16) + 3) & ~3; }
-__host__ __device__ constexpr int toep_window_bytes(int NB, int D) { return (kMfmaWaves * 1024 * NB + 16 * D) * 2; }
+__host__ __device__ constexpr int toep_window_bytes(int NB, int D) { return (kMfmaWaves * 1024 * NB + 16 * D) * 2 + kToepTapBytes; }
 // 16-byte units of the window of a work-group running group (jb0, D0) and,
 // if D1 > 0, a narrower group (jb1 >= jb0, D1) after it: every step of both,
 // plus the signal rows read one step past the last, rounded up to whole
@@ -90,7 +103,7 @@ struct ToepGroup {
     int32_t jb;            // first p of step 0: a multiple of 8, <= -M of every scale
     int32_t D;             // K-steps (a multiple of 4); jb + 16 D >= M + 32
     int32_t rows[kToepScales];   // caller rows (-1: none)
-    int64_t frag_off;      // byte offset of step 0 in the Toeplitz fragments
+    int64_t frag_off;      // byte offset of the group's shifted tap copies in the bank
 };
 
 // ---------------------------------------------------------------------------

@@ -435,7 +435,7 @@ static cwt_status acquire_bank(int dt, int device, const std::vector<double>& sc
 // LDS bytes of a Toeplitz work-group of the bank (its widest group, or its
 // widest bundle of two), and whether it fits the WIN budget.
 static int64_t toep_bytes(const Bank& bk, int NB, int bg) {
-    return 16 * (int64_t)((512 * NB + (bg == 2 ? bk.toep_w2 : bk.toep_w1) + 3) & ~3);
+    return kToepTapBytes + 16 * (int64_t)((512 * NB + (bg == 2 ? bk.toep_w2 : bk.toep_w1) + 3) & ~3);
 }
 static bool toep_fits(const Bank& bk, int NB) { return toep_window_bytes(NB, toep_steps(bk.Mmax)) + 64 <= kWinBudget; }
 
@@ -463,7 +463,7 @@ static cwt_status ensure_toep(Bank& bk) {
         G.jb = toep_jb(Mg);
         G.D = toep_steps(Mg);
         G.frag_off = off;
-        off += (int64_t)G.D * kToepScales * 1024;
+        off += toep_group_bytes(G.D);
         dmax = std::max(dmax, G.D);
     }
     std::vector<double> sorted(S);

@@ -1051,11 +1051,11 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
 // so every K-step d is one MFMA  C[i][j] += X_d[i][u] * T_d[u][j]  with
 //     X_d[i][u] = x~[k1 + 32 i + jb + 16 d + u]   (strided rows of the staged
 //                 window: a lane reads 8 consecutive samples, 16-byte aligned)
-//     T_d[u][j] = t[jb + 16 d + u - j]             (a Toeplitz block of the taps,
-//                 stored in the bank in the B operand's lane order).
+//     T_d[u][j] = t[jb + 16 d + u - j]             (a Toeplitz block of the taps:
+//                 one aligned 16-byte unit of a shifted copy per lane).
 // The signal fragment of a step serves every scale of the wave and the tap
 // fragment every block, so a wave holding kToepScales scales x NB blocks
-// issues kToepScales * NB MFMAs per kToepScales + NB fragment loads (the
+// issues kToepScales * NB MFMAs per kToepScales + NB LDS fragment reads (the
 // 32-scale blocks of the other tiles share one tap fragment between at most
 // A frame blocks and pad every scale to its block's widest range).  The K
 // range of a scale group starts at jb (<= -M, a multiple of 8) and spans D
@@ -1063,6 +1063,13 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
 // steps in ascending d in one accumulator, so the result depends neither on
 // NB nor on the launch.  A work-group (4 waves) owns 4 * 1024 * NB
 // consecutive frames of one clip and one scale group.
+//
+// The taps reach the K loop through LDS: the work-group copies the units of
+// the next kToepChunk steps (the group's shifted copies, 17 KiB for 32 steps
+// and two scales, against 64 KiB of fragments per wave when every wave loaded
+// its own from L2) into the free one of two buffers while it runs the
+// current chunk, with one barrier per chunk.  LDS holds the two tap buffers
+// (kToepTapBytes) and then the signal window.
 
 // 16-byte unit u of a Toeplitz window sits at LDS unit u ^ ((u >> 4) & 3):
 // the eight lanes of a 128-bit read pass, 4 units apart, then fall on eight
@@ -1093,22 +1100,53 @@ __device__ __forceinline__ void toep_stage(const ClipArg& c, int64_t j0, int nun
     }
 }
 
+// Tap chunks.  Chunk c of group G is units k = 2 c kToepChunk + kk,
+// kk < kToepChunkK, of every copy of both scales, in LDS as
+// [scale][kk][copy]; the eight lanes of a read pass (fixed l / 8) then read
+// eight different copies of one unit: eight different 16-byte slots.
+constexpr int kToepFetch = (kToepChunkUnits + kMfmaWaves * kWaveSize - 1) / (kMfmaWaves * kWaveSize);
+
+__device__ __forceinline__ void toep_fetch(const MfmaArgs& a, const ToepGroup* __restrict__ G, int c,
+                                           i32x4 (&pre)[kToepFetch]) {
+    const int CL = toep_copy_units(G->D), k0 = 2 * kToepChunk * c;
+    const uint8_t* __restrict__ base = a.tfrags + G->frag_off;
+#pragma unroll
+    for (int i = 0; i < kToepFetch; ++i) {
+        const int x = threadIdx.x + i * kMfmaWaves * kWaveSize;
+        const int sc = x >= kToepChunkK * 8 ? 1 : 0, xs = x - sc * kToepChunkK * 8;
+        if (x < kToepChunkUnits && k0 + xs / 8 < CL)
+            pre[i] = *(const i32x4*)(base + ((int64_t)(sc * CL + k0) * 8 + xs) * 16);
+        else
+            pre[i] = i32x4{0, 0, 0, 0};
+    }
+}
+
+__device__ __forceinline__ void toep_put(uint8_t* buf, const i32x4 (&pre)[kToepFetch]) {
+#pragma unroll
+    for (int i = 0; i < kToepFetch; ++i) {
+        const int x = threadIdx.x + i * kMfmaWaves * kWaveSize;
+        if (x < kToepChunkUnits) *(i32x4*)(buf + x * 16) = pre[i];
+    }
+}
+
 // The K loop and epilogue of one scale group over the wave's frames
-// kw .. kw + 1024 NB - 1, from the staged window (16-byte unit ubase is row
-// i = lane % 32, K half lane / 32, of step 0, block 0).  tp holds the group's
-// first PF steps of tap fragments on entry; `next`, when not null, is the
-// group run after this one: its first PF steps are loaded into tp right
-// after the loop, ahead of this group's stores.
-template <int DT, int NB, int PF>
+// kw .. kw + 1024 NB - 1, from the staged window `win` (16-byte unit ubase is
+// row i = lane % 32, K half lane / 32, of step 0, block 0) and the tap
+// buffers `taps`, whose buffer 0 holds the group's chunk 0 (visible to every
+// wave) on entry.  Every wave of the work-group runs the chunks and their
+// barriers; a wave whose frames lie past the clip (`active` false) skips the
+// MFMAs and stores.
+template <int DT, int NB>
 __device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, const ToepGroup* __restrict__ G,
-                                           const ToepGroup* __restrict__ next, int64_t kw, int ubase,
-                                           const uint8_t* lds, i32x4 (&tp)[PF][kToepScales]) {
+                                           int64_t kw, int ubase, bool active, const uint8_t* win, uint8_t* taps) {
     constexpr int TS = kToepScales;
-    static_assert(PF == 4 || PF == 8, "prefetch depth of 4 or 8 steps");
+    constexpr int CB = kToepChunkUnits * 16;   // bytes per tap buffer
     const int lane = threadIdx.x & 63;
     const int D = G->D;
-    const uint8_t* __restrict__ tb = a.tfrags + G->frag_off + lane * 16;
-    i32x4 sg[2][NB];
+    const int nch = (D + kToepChunk - 1) / kToepChunk;
+    // lane's unit at local step 0: copy (j mod 8) of unit 2 d + h - j / 8 + 3 (j = l % 32, h = l / 32)
+    const int tu = ((lane >> 5) - ((lane & 31) >> 3) + 3) * 8 + (lane & 7);
+    i32x4 sg[2][NB], tp[2][TS];
     f32x16 acc[TS][NB];
 #pragma unroll
     for (int s = 0; s < TS; ++s)
@@ -1117,45 +1155,55 @@ __device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, 
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[s][b][v] = 0.0f;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) sg[0][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b) * 16);
-    // one K-step d in tap slot j (= d mod PF) and signal buffer j & 1
-    auto step = [&](const int j, const int d) __attribute__((always_inline)) {
-        // the next step's signal rows (step D, read last, lies inside the
-        // window), issued first so that they land during this step's MFMAs
+    for (int b = 0; b < NB; ++b) sg[0][b] = *(const i32x4*)(win + toep_swz(ubase + 128 * b) * 16);
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            sg[(j + 1) & 1][b] = *(const i32x4*)(lds + toep_swz(ubase + 128 * b + 2 * (d + 1)) * 16);
+    for (int s = 0; s < TS; ++s) tp[0][s] = *(const i32x4*)(taps + (s * kToepChunkK * 8 + tu) * 16);
+    for (int ch = 0; ch < nch; ++ch) {
+        const int d0 = ch * kToepChunk, steps = min(kToepChunk, D - d0);   // a multiple of 4
+        const bool more = ch + 1 < nch;
+        i32x4 pre[kToepFetch];
+        if (more) toep_fetch(a, G, ch + 1, pre);
+        const uint8_t* cur = taps + (ch & 1) * CB;
+        if (active) {
+            // one K-step d = d0 + q + jo from register buffers jo & 1 (q is a
+            // multiple of 4, jo a constant)
+            auto step = [&](const int q, const int jo) __attribute__((always_inline)) {
+                const int jj = q + jo, d = d0 + jj;
+                // the next step's signal rows (step D, read last, lies inside
+                // the window) and taps (the chunk's last step re-reads its own),
+                // issued first so that they land during this step's MFMAs
 #pragma unroll
-        for (int s = 0; s < TS; ++s)
+                for (int b = 0; b < NB; ++b)
+                    sg[(jo + 1) & 1][b] = *(const i32x4*)(win + toep_swz(ubase + 128 * b + 2 * (d + 1)) * 16);
+                const int jn = min(jj + 1, steps - 1);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) acc[s][b] = mma<DT>(&sg[j & 1][b], &tp[j][s], acc[s][b]);
-        // taps PF steps ahead into the registers this step consumed
-        const int dn = min(d + PF, D - 1);
+                for (int s = 0; s < TS; ++s)
+                    tp[(jo + 1) & 1][s] = *(const i32x4*)(cur + (s * kToepChunkK * 8 + tu + 16 * jn) * 16);
 #pragma unroll
-        for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(tb + (int64_t)(TS * dn + s) * 1024);
-        // pin that order (left alone, the scheduler sinks every load next to
-        // its first use and waits for it there)
-        __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);        // DS read
-        __builtin_amdgcn_sched_group_barrier(0x008, TS * NB, 0);   // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x020, TS, 0);        // VMEM read
-    };
-    int d0 = 0;
-    for (; d0 + PF <= D; d0 += PF) {
+                for (int s = 0; s < TS; ++s)
 #pragma unroll
-        for (int j = 0; j < PF; ++j) step(j, d0 + j);
+                    for (int b = 0; b < NB; ++b) acc[s][b] = mma<DT>(&sg[jo & 1][b], &tp[jo & 1][s], acc[s][b]);
+                // pin that order (left alone, the scheduler sinks every read
+                // next to its first use and waits for it there)
+                __builtin_amdgcn_sched_group_barrier(0x100, NB + TS, 0);   // DS read
+                __builtin_amdgcn_sched_group_barrier(0x008, TS * NB, 0);   // MFMA
+            };
+            for (int q = 0; q < steps; q += 4) {
+                step(q, 0);
+                step(q, 1);
+                step(q, 2);
+                step(q, 3);
+            }
+        }
+        if (more) {
+            uint8_t* nxt = taps + ((ch + 1) & 1) * CB;
+            toep_put(nxt, pre);
+            lds_barrier();
+#pragma unroll
+            for (int s = 0; s < TS; ++s) tp[0][s] = *(const i32x4*)(nxt + (s * kToepChunkK * 8 + tu) * 16);
+        }
     }
-    if (d0 < D) {   // D is a multiple of 4: a last half round (PF = 8)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) step(j, d0 + j);
-    }
-    if (next) {
-        const uint8_t* __restrict__ nb = a.tfrags + next->frag_off + lane * 16;
-        const int Dn = next->D;
-#pragma unroll
-        for (int j = 0; j < PF; ++j)
-#pragma unroll
-            for (int s = 0; s < TS; ++s) tp[j][s] = *(const i32x4*)(nb + (int64_t)(TS * min(j, Dn - 1) + s) * 1024);
-    }
+    if (!active) return;
     // Epilogue: lane column j = lane % 32, rows i = 8 (v / 4) + 4 (lane / 32) + v % 4:
     // for each v the 32 lanes of a half-wave store 32 consecutive frames.
     const int r = lane & 31, hg = lane >> 5;
@@ -1182,8 +1230,9 @@ __device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, 
 
 // One Toeplitz work-group tile: frames tile * 4096 NB .. of one clip against
 // one scale group, or two (g1 >= 0) run one after the other over one staged
-// window (sized for the wider, g0).
-template <int DT, int NB, int PF>
+// window (sized for the wider, g0).  Every wave of the work-group runs to the
+// end (the tap chunks take all four to load and to pass their barriers).
+template <int DT, int NB>
 __device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipArg& c, int tile, int g0, int g1,
                                                   uint8_t* lds) {
     static_assert(DT == DT_BF16 || DT == DT_FP16, "Toeplitz tiles hold 16-bit operands");
@@ -1194,26 +1243,31 @@ __device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipA
     const ToepGroup* __restrict__ G1 = g1 >= 0 ? a.tgroups + g1 : nullptr;
     const int64_t k0 = (int64_t)tile * (kMfmaWaves * FW);
     const bool al16 = (((uintptr_t)c.x) & 15) == 0;
-    // the window starts at g0's jb; g1 (narrower: jb1 >= jb0) reads it from
-    // an offset of (jb1 - jb0) / 8 units, its steps reaching up to 3 units
-    // past g0's (toep_window_units)
-    toep_stage<DT>(c, k0 + G0->jb, toep_window_units(NB, G0->jb, G0->D, G1 ? G1->jb : G0->jb, G1 ? G1->D : 0),
-                   al16, lds);
+    uint8_t* taps = lds;
+    uint8_t* win = lds + kToepTapBytes;
+    {
+        i32x4 pre[kToepFetch];
+        toep_fetch(a, G0, 0, pre);
+        // the window starts at g0's jb; g1 (narrower: jb1 >= jb0) reads it from
+        // an offset of (jb1 - jb0) / 8 units, its steps reaching up to 3 units
+        // past g0's (toep_window_units)
+        toep_stage<DT>(c, k0 + G0->jb, toep_window_units(NB, G0->jb, G0->D, G1 ? G1->jb : G0->jb, G1 ? G1->D : 0),
+                       al16, win);
+        toep_put(taps, pre);
+    }
     lds_barrier();
     const int64_t kw = k0 + (int64_t)w * FW;
-    if (kw >= c.K) return;   // the clip ends before this wave's frames
+    const bool active = kw < c.K;   // the clip ends before this wave's frames
     const int ubase = (w * FW) / 8 + 4 * (lane & 31) + (lane >> 5);
-    i32x4 tp[PF][kToepScales];
-    {
-        const uint8_t* __restrict__ tb = a.tfrags + G0->frag_off + lane * 16;
-#pragma unroll
-        for (int j = 0; j < PF; ++j)
-#pragma unroll
-            for (int s = 0; s < kToepScales; ++s)
-                tp[j][s] = *(const i32x4*)(tb + (int64_t)(kToepScales * min(j, G0->D - 1) + s) * 1024);
+    toep_group<DT, NB>(a, c, G0, kw, ubase, active, win, taps);
+    if (G1) {
+        lds_barrier();   // every wave is done with g0's tap buffers
+        i32x4 pre[kToepFetch];
+        toep_fetch(a, G1, 0, pre);
+        toep_put(taps, pre);
+        lds_barrier();
+        toep_group<DT, NB>(a, c, G1, kw, ubase + (G1->jb - G0->jb) / 8, active, win, taps);
     }
-    toep_group<DT, NB, PF>(a, c, G0, G1, kw, ubase, lds, tp);
-    if (G1) toep_group<DT, NB, PF>(a, c, G1, nullptr, kw, ubase + (G1->jb - G0->jb) / 8, lds, tp);
 }
 
 // Work-group id -> (frame tile, scale groups).  With bundles (bg = 2) a
@@ -1292,7 +1346,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     extern __shared__ __align__(16) uint8_t lds[];
     int g0, g1, tile;
     toep_unit(blockIdx.x, a.ntgroups, a.toep_bg, a.clip.ntile, &g0, &g1, &tile);
-    process_tile_toep<DT, NB, kToepPrefetch>(a, a.clip, tile, g0, g1, lds);
+    process_tile_toep<DT, NB>(a, a.clip, tile, g0, g1, lds);
 }
 
 // Toeplitz tiles of a batch of hop-1 clips in one grid.  The frame tiles of
@@ -1314,7 +1368,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const ClipArg c = a.clips[lo];
-    process_tile_toep<DT, 4, kToepPrefetch>(a, c, t - a.tile_prefix[lo] / ntg, g0, -1, lds);
+    process_tile_toep<DT, 4>(a, c, t - a.tile_prefix[lo] / ntg, g0, -1, lds);
 }
 
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
@@ -1348,7 +1402,7 @@ __device__ __forceinline__ void persistent_body(const MfmaArgs& a, uint8_t* lds,
                 if (c.mode == STAGE_TOEP) {
                     int g0, g1, tile;
                     toep_unit(local, a.ntgroups, a.toep_bg, c.ntile, &g0, &g1, &tile);
-                    process_tile_toep<DT, kToepBatchNB, 4>(a, c, tile, g0, g1, lds);
+                    process_tile_toep<DT, kToepBatchNB>(a, c, tile, g0, g1, lds);
                     lds_barrier();
                     continue;
                 }
