@@ -34,6 +34,13 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Clip signals and outputs are device (global) memory, reached through
+// pointers the compiler cannot place: accessed through these, they compile to
+// global rather than flat instructions (a flat access also counts on the LDS
+// counter, so a later wait for LDS reads would wait for it as well).
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) f32x4 gf32x4;
 
 template <int DT>
 struct Tr {
@@ -132,15 +139,15 @@ __device__ __forceinline__ void load_span(const float* __restrict__ x, int64_t l
     if (j >= 0 && j + CNT <= len && al16 && (j & 3) == 0) {
 #pragma unroll
         for (int e = 0; e < CNT; e += 4) {
-            float4 f4 = *(const float4*)(x + j + e);
-            v[OFF + e] = f4.x; v[OFF + e + 1] = f4.y; v[OFF + e + 2] = f4.z; v[OFF + e + 3] = f4.w;
+            const f32x4 f4 = *(const gf32x4*)((const gfloat*)x + j + e);
+            v[OFF + e] = f4[0]; v[OFF + e + 1] = f4[1]; v[OFF + e + 2] = f4[2]; v[OFF + e + 3] = f4[3];
         }
     } else {
 #pragma unroll
         for (int e = 0; e < CNT; ++e) {
             const int64_t jj = j + e;
             const int64_t jc = jj < 0 ? 0 : (jj >= len ? len - 1 : jj);
-            const float t = x[jc];
+            const float t = ((const gfloat*)x)[jc];
             v[OFF + e] = (jj >= 0 && jj < len) ? t : 0.0f;
         }
     }
@@ -754,7 +761,7 @@ __device__ __forceinline__ void store_rows(const RowMap<DT>& m, const f32x16& ac
         // also for a clip so faint that inv_beta sits at 2^-126
         if constexpr (DT == DT_FP8) val = val * m.scale[v] * inv_beta;
         if (!signed_out) val = fabsf(val);
-        __builtin_nontemporal_store(val, out + (int64_t)m.row[v] * K + k);
+        __builtin_nontemporal_store(val, (gfloat*)out + (int64_t)m.row[v] * K + k);
     }
 }
 
@@ -1077,10 +1084,9 @@ __device__ __forceinline__ void process_tile_win(const MfmaArgs& a, const ClipAr
 __device__ __forceinline__ int toep_swz(int u) { return u ^ ((u >> 4) & 3); }
 
 // x~[j0 + 8 u .. j0 + 8 u + 8) converted to the operand type, for u < nunits;
-// four units per thread in flight.
-template <int DT>
+// R units per thread in flight.
+template <int DT, int R = 4>
 __device__ __forceinline__ void toep_stage(const ClipArg& c, int64_t j0, int nunits, bool al16, uint8_t* lds) {
-    constexpr int R = 4;
     for (int u0 = threadIdx.x; u0 < nunits; u0 += R * kMfmaWaves * kWaveSize) {
         float v[R][8];
 #pragma unroll
@@ -1129,16 +1135,15 @@ __device__ __forceinline__ void toep_put(uint8_t* buf, const i32x4 (&pre)[kToepF
     }
 }
 
-// The K loop and epilogue of one scale group over the wave's frames
-// kw .. kw + 1024 NB - 1, from the staged window `win` (16-byte unit ubase is
-// row i = lane % 32, K half lane / 32, of step 0, block 0) and the tap
-// buffers `taps`, whose buffer 0 holds the group's chunk 0 (visible to every
-// wave) on entry.  Every wave of the work-group runs the chunks and their
-// barriers; a wave whose frames lie past the clip (`active` false) skips the
-// MFMAs and stores.
+// The K loop of one scale group over the wave's frames, into acc, from the
+// staged window `win` (16-byte unit ubase is row i = lane % 32, K half
+// lane / 32, of step 0, block 0) and the tap buffers `taps`, whose buffer 0
+// holds the group's chunk 0 (visible to every wave) on entry.  Every wave of
+// the work-group runs the chunks and their barriers; a wave whose frames lie
+// past the clip (`active` false) skips the MFMAs.
 template <int DT, int NB>
-__device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, const ToepGroup* __restrict__ G,
-                                           int64_t kw, int ubase, bool active, const uint8_t* win, uint8_t* taps) {
+__device__ __forceinline__ void toep_loop(const MfmaArgs& a, const ToepGroup* __restrict__ G, int ubase, bool active,
+                                          const uint8_t* win, uint8_t* taps, f32x16 (&acc)[kToepScales][NB]) {
     constexpr int TS = kToepScales;
     constexpr int CB = kToepChunkUnits * 16;   // bytes per tap buffer
     const int lane = threadIdx.x & 63;
@@ -1147,7 +1152,6 @@ __device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, 
     // lane's unit at local step 0: copy (j mod 8) of unit 2 d + h - j / 8 + 3 (j = l % 32, h = l / 32)
     const int tu = ((lane >> 5) - ((lane & 31) >> 3) + 3) * 8 + (lane & 7);
     i32x4 sg[2][NB], tp[2][TS];
-    f32x16 acc[TS][NB];
 #pragma unroll
     for (int s = 0; s < TS; ++s)
 #pragma unroll
@@ -1203,29 +1207,89 @@ __device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, 
             for (int s = 0; s < TS; ++s) tp[0][s] = *(const i32x4*)(nxt + (s * kToepChunkK * 8 + tu) * 16);
         }
     }
-    if (!active) return;
-    // Epilogue: lane column j = lane % 32, rows i = 8 (v / 4) + 4 (lane / 32) + v % 4:
-    // for each v the 32 lanes of a half-wave store 32 consecutive frames.
-    const int r = lane & 31, hg = lane >> 5;
+}
+
+// Epilogue through LDS: half a 1024-frame block at a time, the wave writes its
+// accumulators into its 2.5 KiB slice of `scr` (row i of 32 frames at float
+// i * kToepTrRow: the two half-waves' writes fall on different banks) and
+// reads them back four consecutive frames per lane, so that one 16-byte store
+// per lane covers 1 KiB of a row: 32 stores per wave for two scales and four
+// blocks, against 128 of 4 bytes (a wave keeps at most 63 memory
+// instructions in flight, so the 4-byte form waits for half of its own stores).
+constexpr int kToepTrRow = 40;
+constexpr int kToepTrBytes = kMfmaWaves * 16 * kToepTrRow * 4;
+static_assert(kToepTrBytes <= kToepChunkUnits * 16, "the transposes fit one tap buffer");
+
+template <int NB>
+__device__ __forceinline__ void toep_store_tr(const MfmaArgs& a, const ClipArg& c, const ToepGroup* __restrict__ G,
+                                              int64_t kw, const f32x16 (&acc)[kToepScales][NB], float* scr) {
+    constexpr int TS = kToepScales;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 31, hg = lane >> 5;
+    float* my = scr + (threadIdx.x >> 6) * 16 * kToepTrRow;
+    const float* rd = my + (lane >> 3) * kToepTrRow + 4 * (lane & 7);
 #pragma unroll
     for (int s = 0; s < TS; ++s) {
         const int row = G->rows[s];
         if (row < 0) continue;
-        float* __restrict__ orow = c.out + (int64_t)row * c.K;
+        gfloat* __restrict__ orow = (gfloat*)c.out + (int64_t)row * c.K;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int64_t kb0 = kw + 1024 * b + r;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t k = kb0 + 32 * (8 * (v >> 2) + 4 * hg + (v & 3));
-                if (k < c.K) {
-                    float val = acc[s][b][v];
-                    if (!a.signed_out) val = fabsf(val);
-                    __builtin_nontemporal_store(val, orow + k);
+            for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+                for (int vv = 0; vv < 8; ++vv) {
+                    const int v = 8 * hh + vv;
+                    const int i = 8 * (v >> 2) + 4 * hg + (v & 3) - 16 * hh;
+                    const float val = acc[s][b][v];
+                    my[i * kToepTrRow + j] = a.signed_out ? val : fabsf(val);
+                }
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const f32x4 o = *(const f32x4*)(rd + 8 * g * kToepTrRow);
+                    const int64_t k = kw + 1024 * b + 512 * hh + 256 * g + 4 * lane;
+                    gfloat* dst = orow + k;
+                    if (k + 3 < c.K && (((uintptr_t)dst) & 15) == 0) {
+                        __builtin_nontemporal_store(o, (gf32x4*)dst);
+                    } else {
+                        if (k < c.K) __builtin_nontemporal_store(o[0], dst);
+                        if (k + 1 < c.K) __builtin_nontemporal_store(o[1], dst + 1);
+                        if (k + 2 < c.K) __builtin_nontemporal_store(o[2], dst + 2);
+                        if (k + 3 < c.K) __builtin_nontemporal_store(o[3], dst + 3);
+                    }
                 }
             }
         }
     }
+}
+
+// One scale group over the wave's frames: the K loop, then (once every wave
+// is done with the tap buffers) the epilogue through tap buffer 1.
+template <int DT, int NB>
+__device__ __forceinline__ void toep_group(const MfmaArgs& a, const ClipArg& c, const ToepGroup* __restrict__ G,
+                                           int64_t kw, int ubase, bool active, const uint8_t* win, uint8_t* taps) {
+    f32x16 acc[kToepScales][NB];
+    toep_loop<DT, NB>(a, G, ubase, active, win, taps, acc);
+    lds_barrier();
+    if (active) toep_store_tr<NB>(a, c, G, kw, acc, (float*)(taps + kToepChunkUnits * 16));
+}
+
+// Stage a tile starting at frame k0 for group G0 (and a narrower G1 run
+// after it over the same window): the window of its signal and chunk 0 of
+// G0's taps, into LDS (no barrier).  R: window units per thread in flight.
+template <int DT, int NB, int R = 4>
+__device__ __forceinline__ void toep_tile_stage(const MfmaArgs& a, const ClipArg& c, int64_t k0,
+                                                const ToepGroup* __restrict__ G0, const ToepGroup* __restrict__ G1,
+                                                uint8_t* lds) {
+    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
+    i32x4 pre[kToepFetch];
+    toep_fetch(a, G0, 0, pre);
+    // the window starts at g0's jb; g1 (narrower: jb1 >= jb0) reads it from
+    // an offset of (jb1 - jb0) / 8 units, its steps reaching up to 3 units
+    // past g0's (toep_window_units)
+    toep_stage<DT, R>(c, k0 + G0->jb, toep_window_units(NB, G0->jb, G0->D, G1 ? G1->jb : G0->jb, G1 ? G1->D : 0),
+                      al16, lds + kToepTapBytes);
+    toep_put(lds, pre);
 }
 
 // One Toeplitz work-group tile: frames tile * 4096 NB .. of one clip against
@@ -1242,19 +1306,9 @@ __device__ __forceinline__ void process_tile_toep(const MfmaArgs& a, const ClipA
     const ToepGroup* __restrict__ G0 = a.tgroups + g0;
     const ToepGroup* __restrict__ G1 = g1 >= 0 ? a.tgroups + g1 : nullptr;
     const int64_t k0 = (int64_t)tile * (kMfmaWaves * FW);
-    const bool al16 = (((uintptr_t)c.x) & 15) == 0;
     uint8_t* taps = lds;
     uint8_t* win = lds + kToepTapBytes;
-    {
-        i32x4 pre[kToepFetch];
-        toep_fetch(a, G0, 0, pre);
-        // the window starts at g0's jb; g1 (narrower: jb1 >= jb0) reads it from
-        // an offset of (jb1 - jb0) / 8 units, its steps reaching up to 3 units
-        // past g0's (toep_window_units)
-        toep_stage<DT>(c, k0 + G0->jb, toep_window_units(NB, G0->jb, G0->D, G1 ? G1->jb : G0->jb, G1 ? G1->D : 0),
-                       al16, win);
-        toep_put(taps, pre);
-    }
+    toep_tile_stage<DT, NB>(a, c, k0, G0, G1, lds);
     lds_barrier();
     const int64_t kw = k0 + (int64_t)w * FW;
     const bool active = kw < c.K;   // the clip ends before this wave's frames
