@@ -1210,14 +1210,16 @@ __device__ __forceinline__ void toep_loop(const MfmaArgs& a, const ToepGroup* __
 }
 
 // Epilogue through LDS: half a 1024-frame block at a time, the wave writes its
-// accumulators into its 2.5 KiB slice of `scr` (row i of 32 frames at float
-// i * kToepTrRow: the two half-waves' writes fall on different banks) and
-// reads them back four consecutive frames per lane, so that one 16-byte store
-// per lane covers 1 KiB of a row: 32 stores per wave for two scales and four
-// blocks, against 128 of 4 bytes (a wave keeps at most 63 memory
-// instructions in flight, so the 4-byte form waits for half of its own stores).
-constexpr int kToepTrRow = 40;
-constexpr int kToepTrBytes = kMfmaWaves * 16 * kToepTrRow * 4;
+// accumulators into its 2.5 KiB slice of `scr` and reads them back four
+// consecutive frames per lane, so that one 16-byte store per lane covers
+// 1 KiB of a row: 32 stores per wave for two scales and four blocks, against
+// 128 of 4 bytes (a wave keeps at most 63 memory instructions in flight, so
+// the 4-byte form waits for half of its own stores).  Frame f of the half
+// block sits at float f + 16 (f / 64): a 16-lane read pass takes one 64-frame
+// run (64 banks), and the two half-waves' writes (frames 128 apart) fall on
+// opposite halves of the banks.
+constexpr int kToepTrFloats = 512 + 16 * 8;
+constexpr int kToepTrBytes = kMfmaWaves * kToepTrFloats * 4;
 static_assert(kToepTrBytes <= kToepChunkUnits * 16, "the transposes fit one tap buffer");
 
 template <int NB>
@@ -1226,8 +1228,8 @@ __device__ __forceinline__ void toep_store_tr(const MfmaArgs& a, const ClipArg& 
     constexpr int TS = kToepScales;
     const int lane = threadIdx.x & 63;
     const int j = lane & 31, hg = lane >> 5;
-    float* my = scr + (threadIdx.x >> 6) * 16 * kToepTrRow;
-    const float* rd = my + (lane >> 3) * kToepTrRow + 4 * (lane & 7);
+    float* my = scr + (threadIdx.x >> 6) * kToepTrFloats;
+    const float* rd = my + 4 * lane + 16 * (lane >> 4);
 #pragma unroll
     for (int s = 0; s < TS; ++s) {
         const int row = G->rows[s];
@@ -1240,13 +1242,13 @@ __device__ __forceinline__ void toep_store_tr(const MfmaArgs& a, const ClipArg& 
 #pragma unroll
                 for (int vv = 0; vv < 8; ++vv) {
                     const int v = 8 * hh + vv;
-                    const int i = 8 * (v >> 2) + 4 * hg + (v & 3) - 16 * hh;
+                    const int f = 32 * (8 * (v >> 2) + 4 * hg + (v & 3) - 16 * hh) + j;
                     const float val = acc[s][b][v];
-                    my[i * kToepTrRow + j] = a.signed_out ? val : fabsf(val);
+                    my[f + 16 * (f >> 6)] = a.signed_out ? val : fabsf(val);
                 }
 #pragma unroll
                 for (int g = 0; g < 2; ++g) {
-                    const f32x4 o = *(const f32x4*)(rd + 8 * g * kToepTrRow);
+                    const f32x4 o = *(const f32x4*)(rd + 320 * g);
                     const int64_t k = kw + 1024 * b + 512 * hh + 256 * g + 4 * lane;
                     gfloat* dst = orow + k;
                     if (k + 3 < c.K && (((uintptr_t)dst) & 15) == 0) {
