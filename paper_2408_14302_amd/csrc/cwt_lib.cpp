@@ -803,8 +803,15 @@ static const int kToepBatchCfg = 14;   // kMfmaCfgs[14].A == kToepBatchNB
 // scales, hops 1-256): the best configuration or within a few percent of it
 // in every case, where a fixed one is up to 2x slower.  BF16/FP16/BF16x3
 // results do not depend on the configuration.
+// For a hop-1 clip of a Toeplitz plan the set is 13, 14, 15 (Toeplitz tiles
+// of 16384, 8192 and 4096 frames) and the bar four work-groups per CU: one
+// 10 s clip with 128 linear scales ran in 48.4 / 46.7 / 47.0 us under
+// 13 / 14 / 15, a 5 s clip in 33.5 / 28.3 / 25.6 and a 30 s clip in 121.7 /
+// 125.0 / 131.7 (with taps through LDS, whose per-work-group barriers favour
+// more and shorter items where a launch has under two rounds of them).
 static const int kAutoCfgs[3] = {6, 4, 5};
-static const int kAutoToep[3] = {13, 14, 15};   // Toeplitz tiles of 16384, 8192, 4096 frames
+static const int kAutoToep[3] = {13, 14, 15};
+static const int kAutoPerCu = 2, kAutoToepPerCu = 4;
 
 static void set_auto(cwt_plan_s* p) {
     g_cfg_epoch.fetch_add(1);
@@ -821,7 +828,8 @@ static void set_auto(cwt_plan_s* p) {
 template <class WG>
 static int auto_cfg(const cwt_plan_s* p, WG&& wgs) {
     if (!p->cfg_auto) return p->cfg;
-    const int64_t need = 2 * (int64_t)std::max(1, p->cus);
+    const int per_cu = kMfmaCfgs[p->auto_set[0]].toep ? kAutoToepPerCu : kAutoPerCu;
+    const int64_t need = per_cu * (int64_t)std::max(1, p->cus);
     for (int i = 0; i < 3; ++i) {
         const ClipLayout& L = p->auto_lay[i];
         if (L.s.mode != STAGE_WIN && L.s.mode != STAGE_TOEP) continue;
