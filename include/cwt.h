@@ -217,8 +217,9 @@ int32_t cwt_plan_num_configs(cwt_plan_t plan);
  * kind (and between a clip alone and in a batch); the two kinds sum each
  * coefficient's products in different groups of 16 and agree within the
  * dtype's tolerance.  A batch runs a Toeplitz plan's clips as Toeplitz tiles:
- * configuration 13's in one grid when every clip of the batch is one, else
- * configuration 14's in the persistent kernel. */
+ * in one grid when every clip of the batch is one (configuration 13's, 14's
+ * or 15's, the first that gives four work-groups per CU), else configuration
+ * 14's in the persistent kernel. */
 int32_t cwt_plan_config_kind(cwt_plan_t plan, int32_t index);
 cwt_status cwt_plan_set_config(cwt_plan_t plan, int32_t index);
 

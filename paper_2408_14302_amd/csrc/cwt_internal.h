@@ -181,9 +181,10 @@ int mfma_max_lds_bytes();
 // Toeplitz tiles of one clip (a.clip, mode STAGE_TOEP): NB = 1, 2 or 4
 // 1024-frame blocks per wave, grid = a.ntgroups * a.clip.ntile.
 hipError_t launch_toep(int dt, int NB, const MfmaArgs& a, int grid, hipStream_t s);
-// Toeplitz tiles (NB = 4) of a batch of hop-1 clips in one grid: a.clips,
-// a.tile_prefix (tiles x groups per clip), a.nclips, grid = a.total_tiles.
-hipError_t launch_toep_batch(int dt, const MfmaArgs& a, int grid, hipStream_t s);
+// Toeplitz tiles (NB = 1, 2 or 4) of a batch of hop-1 clips in one grid:
+// a.clips, a.tile_prefix (tiles x groups per clip), a.nclips, grid =
+// a.total_tiles.
+hipError_t launch_toep_batch(int dt, int NB, const MfmaArgs& a, int grid, hipStream_t s);
 int toep_occupancy(int dt, int NB, size_t shm);
 // Allow every MFMA kernel the full dynamic LDS; call once, outside graph capture.
 hipError_t mfma_init_attributes();

@@ -813,6 +813,20 @@ static const int kAutoCfgs[3] = {6, 4, 5};
 static const int kAutoToep[3] = {13, 14, 15};
 static const int kAutoPerCu = 2, kAutoToepPerCu = 4;
 
+// The tiles of a batch of Toeplitz clips only (one grid of them): the first
+// of 13, 14, 15 that gives the launch kAutoToepPerCu work-groups per CU,
+// else 15 (frames(j): frames of clip j of n).
+template <class FR>
+static int toep_batch_cfg(const Bank& bk, int cus, int n, FR&& frames) {
+    for (int i = 0; i < 3; ++i) {
+        const int64_t F = (int64_t)kMfmaWaves * 1024 * kMfmaCfgs[kAutoToep[i]].A;
+        int64_t t = 0;
+        for (int j = 0; j < n; ++j) t += (frames(j) + F - 1) / F * (int64_t)bk.tgroups.size();
+        if (t >= (int64_t)kAutoToepPerCu * std::max(1, cus)) return kAutoToep[i];
+    }
+    return kAutoToep[2];
+}
+
 static void set_auto(cwt_plan_s* p) {
     g_cfg_epoch.fetch_add(1);
     p->cfg_auto = true;
@@ -1207,7 +1221,8 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
     // the every-layout persistent kernel with kToepBatchNB blocks per wave.
     bool toep_only = !fp32;
     for (int j = 0; j < nc; ++j) toep_only = toep_only && plan_toep(plans[sc.order[j]]);
-    const MfmaCfg& ct = kMfmaCfgs[toep_only ? kToepCfg0 : kToepBatchCfg];
+    const int tcfg = toep_only ? toep_batch_cfg(bk, cus, nc, [&](int j) { return lens[sc.order[j]]; }) : kToepBatchCfg;
+    const MfmaCfg& ct = kMfmaCfgs[tcfg];
     // Longest first (most tiles first) so the persistent grid drains evenly.
     int64_t maxbuf = 16, maxraw = 0, maxwin = 0;
     for (int j = 0; j < nc; ++j) {
@@ -1281,8 +1296,9 @@ static cwt_status batch_prepare(const cwt_plan_t* plans, const float* const* xs,
         a.ntgroups = (int)bk.tgroups.size();
         a.toep_bg = kMfmaCfgs[kToepBatchCfg].wb;
     }
-    if (toep_only) {
+    if (toep_only) {   // one grid of the clips' tiles, ct.A 1024-frame blocks per wave
         bl->pkind = 4;
+        bl->A = ct.A;
         bl->grid = (int)total;
         return CWT_OK;
     }
@@ -1314,7 +1330,7 @@ static hipError_t batch_launch(const BatchLaunch& bl, const uint8_t* dd, hipStre
     if (bl.fp32)
         return launch_direct_batch(bl.d, (const ClipArg*)(dd + 16), (const int32_t*)(dd + 16 + sizeof(ClipArg) * bl.nc),
                                    bl.nc, (int)bl.total, stream);
-    if (bl.pkind == 4) return launch_toep_batch(bl.dt, bl.a, bl.grid, stream);
+    if (bl.pkind == 4) return launch_toep_batch(bl.dt, bl.A, bl.a, bl.grid, stream);
     return launch_mfma(bl.dt, bl.A, 1, bl.a, bl.pkind, bl.grid, stream);
 }
 
@@ -1708,7 +1724,8 @@ int32_t cwt_plan_launch_config(cwt_plan_t plan, int64_t len, int32_t n_clips) {
     if (!plan || len < 1 || n_clips < 1) return -1;
     if (plan->dt == DT_FP32) return plan->cfg;
     const int64_t K = (len + plan->hop - 1) / plan->hop;
-    if (n_clips > 1 && plan_toep(plan)) return kToepCfg0;   // batches of Toeplitz clips: one grid of its tiles
+    if (n_clips > 1 && plan_toep(plan))   // batches of Toeplitz clips: one grid of these tiles
+        return toep_batch_cfg(*plan->bank, plan->cus, n_clips, [&](int) { return K; });
     const int cfg = auto_cfg(plan, [&](const ClipLayout& L) { return (K + L.F - 1) / L.F * L.groups * n_clips; });
     std::vector<cwt_plan_t> pl(n_clips, plan);
     std::vector<int64_t> ln(n_clips, len);

@@ -1411,7 +1411,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // sequence: the widest groups first across all clips, each XCD one group in
 // eight.  One launch then pays one tail for all its clips, where separate
 // launches each wait for their own widest groups' last work items.
-template <int DT>
+template <int DT, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_toep_batch(MfmaArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     const int ntg = a.ntgroups;
@@ -1424,7 +1424,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const ClipArg c = a.clips[lo];
-    process_tile_toep<DT, 4>(a, c, t - a.tile_prefix[lo] / ntg, g0, -1, lds);
+    process_tile_toep<DT, NB>(a, c, t - a.tile_prefix[lo] / ntg, g0, -1, lds);
 }
 
 // Persistent batch kernel: work-group g takes tiles g, g + G, g + 2G, ...
@@ -1587,11 +1587,11 @@ static hipError_t toep_attr() {
 }
 
 hipError_t mfma_init_attributes() {
-    hipError_t e = hipFuncSetAttribute((const void*)k_toep_batch<DT_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       dyn_lds_max());
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_toep_batch<DT_FP16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                dyn_lds_max());
+    hipError_t e = hipSuccess;
+    for (const void* fn : {(const void*)k_toep_batch<DT_BF16, 1>, (const void*)k_toep_batch<DT_BF16, 2>,
+                           (const void*)k_toep_batch<DT_BF16, 4>, (const void*)k_toep_batch<DT_FP16, 1>,
+                           (const void*)k_toep_batch<DT_FP16, 2>, (const void*)k_toep_batch<DT_FP16, 4>})
+        if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds_max());
     if (e == hipSuccess) e = toep_attr<DT_BF16, 1>();
     if (e == hipSuccess) e = toep_attr<DT_BF16, 2>();
     if (e == hipSuccess) e = toep_attr<DT_BF16, 4>();
@@ -1646,13 +1646,25 @@ static hipError_t launch_toep1(int NB, const MfmaArgs& a, int grid, hipStream_t 
     }
 }
 
-hipError_t launch_toep_batch(int dt, const MfmaArgs& a, int grid, hipStream_t s) {
+template <int DT>
+static void launch_toep_batch1(int NB, const MfmaArgs& a, int grid, hipStream_t s) {
+    const size_t shm = (size_t)a.shm_bytes;
+    if (NB == 4)
+        hipLaunchKernelGGL((k_toep_batch<DT, 4>), dim3(grid), dim3(256), shm, s, a);
+    else if (NB == 2)
+        hipLaunchKernelGGL((k_toep_batch<DT, 2>), dim3(grid), dim3(256), shm, s, a);
+    else
+        hipLaunchKernelGGL((k_toep_batch<DT, 1>), dim3(grid), dim3(256), shm, s, a);
+}
+
+hipError_t launch_toep_batch(int dt, int NB, const MfmaArgs& a, int grid, hipStream_t s) {
     if ((size_t)a.shm_bytes > (size_t)dyn_lds_max() || grid <= 0 || a.ntgroups <= 0) return hipErrorInvalidValue;
+    if (NB != 1 && NB != 2 && NB != 4) return hipErrorInvalidValue;
     (void)hipGetLastError();
     if (dt == DT_BF16)
-        hipLaunchKernelGGL((k_toep_batch<DT_BF16>), dim3(grid), dim3(256), (size_t)a.shm_bytes, s, a);
+        launch_toep_batch1<DT_BF16>(NB, a, grid, s);
     else if (dt == DT_FP16)
-        hipLaunchKernelGGL((k_toep_batch<DT_FP16>), dim3(grid), dim3(256), (size_t)a.shm_bytes, s, a);
+        launch_toep_batch1<DT_FP16>(NB, a, grid, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -465,6 +465,25 @@ def test_batch_of_hop1_clips_in_one_toeplitz_grid(torch, cw, dt):
     assert p.launch_config(160000, len(xs)) == 13
 
 
+@pytest.mark.parametrize("dt", ["bf16", "fp16"])
+def test_small_hop1_batches_take_smaller_toeplitz_tiles(torch, cw, dt):
+    """A batch of hop-1 clips too small to give four work-groups per CU with
+    16384-frame tiles runs 8192- or 4096-frame tiles in its one grid
+    (configurations 14, 15), with the same bits as the clips launched alone,
+    directly and as graph replays."""
+    scales = np.arange(1, 97)   # 48 scale groups
+    p = cw.Plan(16000.0, scales, 1, dt, signed=True)
+    assert p.launch_config(40000, 6) == 14 and p.launch_config(3000, 3) == 15
+    for lens in ([40000] * 6, [3000, 16385, 40000]):
+        xs = [torch.from_numpy(clip(2, 90 + i, n, 0.0)).cuda() for i, n in enumerate(lens)]
+        alone = [p(x) for x in xs]
+        outs = cw.execute_batch([p] * len(xs), xs)
+        g = cw.Batch(8)([p] * len(xs), xs, graph=True)
+        torch.cuda.synchronize()
+        for i, a in enumerate(alone):
+            assert torch.equal(a, outs[i]) and torch.equal(a, g[i]), (dt, lens, i)
+
+
 def test_prepared_batch_follows_configuration_changes(torch, cw):
     """A context runs a prepared launch again without preparing it on the
     host only while its plans, buffers and the configuration state are those
