@@ -45,12 +45,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2408_14302_amd", "csrc", "mfma.hip")
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 TRAFFIC = {
-    "bf16_hop1": {"kernel": "k_toep_batch<1>", "config": 13, "fetch_kib": 8791.8, "write_kib": 240000.0,
-                  "src_sha256": "faacc4538837a36da0741d93b4609cd034f5cca643894eeeb635ce186a3f975e"},
-    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87381.7,
-                    "write_kib": 55842.6, "src_sha256": "faacc4538837a36da0741d93b4609cd034f5cca643894eeeb635ce186a3f975e"},
-    "bf16_mixed": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 58087.9,
-                   "write_kib": 110042.4, "src_sha256": "faacc4538837a36da0741d93b4609cd034f5cca643894eeeb635ce186a3f975e"},
+    "bf16_hop1": {"kernel": "k_toep_batch<1, 4>", "config": 13, "fetch_kib": 8789.0, "write_kib": 240000.0,
+                  "src_sha256": "3dd0011b8713270b373109099a81a6b4be475d4f737e1fe04817a4283beb8068"},
+    "bf16_hop512": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 87342.5,
+                    "write_kib": 55737.2, "src_sha256": "3dd0011b8713270b373109099a81a6b4be475d4f737e1fe04817a4283beb8068"},
+    "bf16_mixed": {"kernel": "k_mfma_persistent_win<1, 2>", "config": 4, "fetch_kib": 58063.6,
+                   "write_kib": 110719.6, "src_sha256": "3dd0011b8713270b373109099a81a6b4be475d4f737e1fe04817a4283beb8068"},
 }
 
 
